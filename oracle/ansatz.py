@@ -1,0 +1,126 @@
+"""PauliNet wavefunction, its coordinate derivatives and the local energy
+(oracle; test infrastructure).
+
+psi(r) = exp(gamma(r) + J(r)) sum_p c_p det[phi~_up] det[phi~_down],
+phi~_{mu i} = phi_mu(r_i) f_{mu i}(r)                (Results, eq. "ansatz")
+
+E_loc = H psi / psi = -1/2 (lap ln|psi| + |grad ln|psi||^2) + V
+                                        (Methods, eq. "monte-carlo"; H is
+                                         the electronic Hamiltonian)
+
+Derivatives: autograd.  grad = d ln|psi| / d r; the Laplacian is the sum over
+the 3N coordinates of the diagonal second derivatives, each taken by a second
+autograd pass.
+
+Readings (listed in the design notes): electrons 0..n_up-1 are spin up;
+A_p^sigma[k, i] = phi~_{mu_p^sigma(k)}(r_i) over the electrons of spin sigma in
+ascending index; an empty spin block has determinant 1; the determinant sum
+is taken in signed log-sum-exp form (ln|psi_d| = -inf, sign 0 on exact
+cancellation).
+
+Parity pins: exact E_loc for hydrogen-like and Gaussian test functions
+through `local_energy_from`; the textbook Slater-Jastrow special case against
+numpy slogdet and analytic Jacobi-formula derivatives; antisymmetry; CI
+scaling; duplicate determinants; empty spin block; nuclear and electronic
+cusps; finite differences of ln|psi| (tests).
+"""
+
+import torch
+
+from .hamiltonian import coulomb_potential, electronic_cusp
+from .network import Params, jastrow_backflow
+from .orbitals import CuspCorrectedOrbitals
+
+
+def local_energy_from(logpsi_fn, potential_fn, r: torch.Tensor):
+    """E_loc for any log|psi| provider: returns (grad [B,N,3], lap [B],
+    E_loc [B]).  logpsi_fn maps r [B,N,3] -> [B] with walkers independent."""
+    r = r.detach().clone().requires_grad_(True)
+    B = r.shape[0]
+    lp = logpsi_fn(r)
+    (g,) = torch.autograd.grad(lp.sum(), r, create_graph=True)
+    gf = g.reshape(B, -1)
+    lap = torch.zeros(B, dtype=r.dtype)
+    for a in range(gf.shape[1]):
+        (h,) = torch.autograd.grad(gf[:, a].sum(), r, retain_graph=True)
+        lap = lap + h.reshape(B, -1)[:, a]
+    V = potential_fn(r.detach())
+    eloc = -0.5 * (lap + (gf.detach() ** 2).sum(-1)) + V
+    return g.detach(), lap.detach(), eloc.detach()
+
+
+class Oracle:
+    """Evaluates the ansatz for one system, network shape and parameter blob."""
+
+    def __init__(self, system, net, params):
+        self.system = system
+        self.net = net
+        self.R = torch.as_tensor(system.nuc_xyz, dtype=torch.float64)
+        self.Z = torch.as_tensor(system.charge, dtype=torch.float64)
+        self.n_up, self.n_down = int(system.n_up), int(system.n_down)
+        self.orbitals = CuspCorrectedOrbitals(system)
+        self.det_up = torch.as_tensor(system.det_up, dtype=torch.long)
+        self.det_down = torch.as_tensor(system.det_down, dtype=torch.long)
+        self.ci = torch.as_tensor(system.ci, dtype=torch.float64)
+        self.set_params(params)
+
+    def set_params(self, params):
+        flat = torch.as_tensor(params, dtype=torch.float64)
+        self.flat = flat
+        self.p = Params(flat, self.R.shape[0], self.system.n_mo, self.net)
+
+    # -- pieces --------------------------------------------------------------
+    def slater_logdets(self, r, f):
+        """Per determinant and spin: (sign, ln|det|) of A_p^sigma."""
+        phi = self.orbitals(r)  # [B, N, M]
+        phit = phi * f
+        out = []
+        for sl, dets in ((slice(0, self.n_up), self.det_up),
+                         (slice(self.n_up, self.n_up + self.n_down), self.det_down)):
+            n = sl.stop - sl.start
+            if n == 0:
+                B, P = r.shape[0], dets.shape[0]
+                out.append((torch.ones(B, P, dtype=r.dtype), torch.zeros(B, P, dtype=r.dtype)))
+                continue
+            blk = phit[:, sl, :]  # [B, n, M]  (electron i, orbital mu)
+            A = blk[:, :, dets].permute(0, 2, 3, 1)  # [B, P, k, i]
+            s, l = torch.linalg.slogdet(A)
+            out.append((s, l))
+        return out
+
+    def log_psi(self, r, params=None):
+        """(ln|psi| [B], sign [B]) for r [B, N, 3]."""
+        if params is not None:
+            p = Params(params, self.R.shape[0], self.system.n_mo, self.net)
+        else:
+            p = self.p
+        gamma = electronic_cusp(r, self.n_up)
+        J, f = jastrow_backflow(r, self.R, self.n_up, p, self.net)
+        (su, lu), (sd, ld) = self.slater_logdets(r, f)
+        lc = torch.log(torch.abs(self.ci))
+        l_p = lc + lu + ld
+        s_p = torch.sign(self.ci) * su * sd
+        m = torch.max(l_p, dim=-1).values
+        m = torch.where(torch.isfinite(m), m, torch.zeros_like(m))
+        S = (s_p * torch.exp(l_p - m[:, None])).sum(-1)
+        log_d = m + torch.log(torch.abs(S))
+        return gamma + J + log_d, torch.sign(S)
+
+    def potential(self, r):
+        return coulomb_potential(r, self.R, self.Z)
+
+    def evaluate(self, r):
+        """Full hot-path outputs: ln|psi|, sign, grad [B,N,3], lap, E_loc."""
+        r = torch.as_tensor(r, dtype=torch.float64)
+        with torch.no_grad():
+            lp, sg = self.log_psi(r)
+        g, lap, el = local_energy_from(lambda x: self.log_psi(x)[0], self.potential, r)
+        return {"logabs": lp, "sign": sg, "grad": g, "lap": lap, "eloc": el}
+
+    def param_grad_logabs(self, r, cotangent):
+        """sum_w cotangent_w * d ln|psi_w| / d theta (value-path adjoint)."""
+        r = torch.as_tensor(r, dtype=torch.float64)
+        th = self.flat.detach().clone().requires_grad_(True)
+        lp, _ = self.log_psi(r, th)
+        (gth,) = torch.autograd.grad((lp * torch.as_tensor(cotangent, dtype=torch.float64)).sum(), th)
+        return gth
