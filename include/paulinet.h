@@ -1,0 +1,173 @@
+/*
+ * paulinet.h -- C ABI of the MI355X (gfx950) PauliNet walker-evaluation
+ * library.
+ *
+ * The library evaluates, for a batch of Monte Carlo walkers r (all electron
+ * positions), the PauliNet wavefunction of Hermann, Schaetzle and Noe
+ * (arXiv:1909.08423, Results eq. "ansatz"):
+ *
+ *   psi(r) = exp(gamma(r) + J(r)) sum_p c_p det[phi~_up] det[phi~_down],
+ *   phi~_{mu i}(r) = phi_mu(r_i) f_{mu i}(r),
+ *
+ * with a Gaussian-orbital baseline phi_mu corrected at the nuclei (Methods,
+ * "Cusp conditions"), the electronic cusp factor gamma (same section), and a
+ * SchNet-style network giving the Jastrow factor J and the backflow f
+ * (Methods, "PauliNet extension of SchNet").  Per walker it returns
+ * ln|psi|, sign psi, the gradient and Laplacian of ln|psi| in the electron
+ * coordinates and the local energy
+ *
+ *   E_loc = -1/2 (lap ln|psi| + |grad ln|psi||^2) + V        (Methods,
+ *                                                    eq. "monte-carlo")
+ *
+ * and, for the VMC update, the parameter gradient of sum_w ct_w ln|psi_w|
+ * (the adjoint needed by the Hermitian estimator, Methods eq. "trainig").
+ *
+ * Conventions
+ *  - Every pointer argument is a DEVICE pointer unless marked [host].
+ *  - Calls enqueue work on the given HIP stream and return; they never
+ *    synchronise.  Errors detectable on the host (null pointers, shapes,
+ *    workspace size) are returned before anything is enqueued; a non-OK
+ *    status means nothing was enqueued.
+ *  - The caller owns every device buffer, including the workspace.  The
+ *    library allocates device memory only in pn_ctx_create (small copies of
+ *    the system tables) and frees it in pn_ctx_destroy.
+ *  - Per-walker numerical outcomes are data, not errors: an exactly
+ *    cancelling determinant sum gives logabs = -inf and sign = 0.
+ *  - Electrons 0..n_up-1 are spin up, the rest spin down.  Coordinates are
+ *    in bohr, energies in hartree.
+ *  - Limits: n_up, n_down <= 32; n_elec <= 64; n_det <= 64; dim_x <= 128;
+ *    dim_z <= 128; n_feat <= 64; shells are s (l = 0) or p (l = 1).
+ *    Anything else returns PN_ERR_UNSUPPORTED_SHAPE.
+ */
+#ifndef PAULINET_H
+#define PAULINET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PN_OK = 0,
+  PN_ERR_INVALID_ARG = 1,
+  PN_ERR_UNSUPPORTED_SHAPE = 2,
+  PN_ERR_WORKSPACE_TOO_SMALL = 4,
+  PN_ERR_DEVICE = 5,
+  PN_ERR_BUDGET = 6
+} pn_status;
+
+/* Arithmetic of the network (distance features, filters, interaction
+ * layers, Jastrow and backflow heads).  Geometry, orbitals, determinants,
+ * their derivatives and E_loc are always FP64. */
+typedef enum {
+  PN_PREC_FP64 = 0,     /* network in FP64                                  */
+  PN_PREC_NET_FP32 = 1, /* network in FP32                                  */
+  PN_PREC_NET_BF16 = 2  /* network dense layers: BF16 operands, FP32 accum.  */
+} pn_precision;
+
+typedef struct pn_ctx pn_ctx; /* opaque; immutable after create */
+
+/* The system (Results, "Hartree-Fock baseline"; Methods, "Computational
+ * details"): nuclei, one primitive Gaussian per shell, MO coefficients and
+ * the determinant expansion.  All arrays are [host] and copied at create. */
+typedef struct {
+  int32_t n_nuc;
+  const double* nuc_xyz;      /* [n_nuc][3]                                */
+  const double* charge;       /* [n_nuc]                                   */
+  int32_t n_up, n_down;
+  int32_t n_shell;
+  const int32_t* shell_center; /* [n_shell] nucleus index                  */
+  const int32_t* shell_l;      /* [n_shell] 0 = s, 1 = p                   */
+  const double* shell_exp;     /* [n_shell] Gaussian exponent              */
+  int32_t n_mo;
+  const double* mo_coeff;      /* [n_basis][n_mo]; n_basis = sum(2l+1),
+                                  basis order = shell order, then x, y, z  */
+  int32_t n_det;
+  const int32_t* det_up;       /* [n_det][n_up] orbital indices            */
+  const int32_t* det_down;     /* [n_det][n_down]                          */
+  const double* ci;            /* [n_det] determinant coefficients c_p     */
+  double cusp_radius;          /* nuclear cusp correction radius; 0 = off  */
+  const double* cusp_nuc_value; /* [n_nuc][n_mo] corrected on-centre s-part
+                                   value at each nucleus (the variational
+                                   nucleus value); NULL = uncorrected s(0) */
+} pn_system_desc;
+
+/* Network shape (Methods, SchNet extension and featurisation; Table 2). */
+typedef struct {
+  int32_t n_feat;     /* K, number of distance features e_k             */
+  double feat_cutoff; /* r_c in mu_k = r_c q_k^2, sigma_k = (1+r_c q_k)/7 */
+  int32_t dim_x;      /* D_x, electron embedding width                  */
+  int32_t dim_z;      /* D_z, message width                             */
+  int32_t n_layers;   /* L, interaction layers                          */
+} pn_net_desc;
+
+/* Create a context: validates shapes, builds the pair and determinant
+ * tables and the nuclear-cusp polynomials on the host, copies them to the
+ * current device.  *out is NULL on error. */
+pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ctx** out);
+void pn_ctx_destroy(pn_ctx* ctx);
+
+/* Number of entries of the flat FP64 parameter blob.  Layout (Linear is
+ * y = x W + b, W stored [in][out] row-major):
+ *   x0[D_x], Y[n_nuc][D_z];
+ *   per layer: for c in (+,-,n): w1W[K][D_z] w1b[D_z] w2W[D_z][D_z] w2b[D_z];
+ *              hW[D_x][D_z] hb[D_z];
+ *              for c in (+,-,n): gW[D_z][D_x] gb[D_x];
+ *   eta:   W1[D_x][D_x] b1[D_x] W2[D_x][D_x] b2[D_x] W3[D_x][1] b3[1];
+ *   kappa: W1[D_x][D_x] b1[D_x] W2[D_x][D_x] b2[D_x] W3[D_x][n_mo] b3[n_mo]. */
+int64_t pn_param_count(const pn_ctx* ctx);
+
+/* Workspace bytes for a call with n_walkers walkers at the given
+ * precision.  Batches larger than the internal walker tile are processed
+ * tile by tile, so the size stops growing at the tile. */
+pn_status pn_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+
+/* Forward evaluation (the hot path).
+ *   r       [B][n_elec][3] FP64 walker positions
+ *   params  [pn_param_count] FP64 parameter blob (converted internally to
+ *           the network precision)
+ *   logabs  [B] ln|psi|          sign [B] in {-1, 0, +1}
+ *   grad    [B][n_elec][3] d ln|psi| / d r, or NULL
+ *   lap     [B] Laplacian of ln|psi|, or NULL
+ *   eloc    [B] local energy, or NULL
+ * If grad, lap and eloc are all NULL only the value pass runs. */
+pn_status pn_eval(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers, const double* r,
+                  const double* params, pn_precision prec, double* logabs, double* sign,
+                  double* grad, double* lap, double* eloc, void* ws, size_t ws_bytes);
+
+/* Value-path adjoint (Methods eq. "trainig" needs only the parameter
+ * gradient of ln|psi|):
+ *   grad_params[t] += sum_w ct_logabs[w] d ln|psi_w| / d theta_t
+ * grad_params is [pn_param_count] FP64 and is ACCUMULATED into.  The
+ * forward values are recomputed inside the call (nothing is stored between
+ * calls).  Per-walker contributions are reduced in a fixed order, so the
+ * result does not depend on what else runs on the device. */
+pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers,
+                           const double* r, const double* params, pn_precision prec,
+                           const double* ct_logabs, double* grad_params, void* ws,
+                           size_t ws_bytes);
+
+/* Per-stage kernel timing, for profiling.  When enabled, pn_eval records
+ * a HIP event before and after each of its stages on the call's stream.
+ * pn_stage_times waits for the recorded events and returns, per stage, the
+ * summed duration in milliseconds and the number of timed launches since
+ * timing was enabled; it synchronises with those events (not for use on a
+ * latency-critical path).  Stages, in order: 0 parameter conversion,
+ * 1 geometry + orbitals, 2 filters, 3 network values, 4 determinants,
+ * 5 network tangents, 6 determinant tangents, 7 finalize.  n_stages of the
+ * output arrays must be >= 8. */
+#define PN_N_STAGES 8
+pn_status pn_stage_timing(pn_ctx* ctx, int enable);
+pn_status pn_stage_times(pn_ctx* ctx, double* ms_sum /*[host]*/, int64_t* count /*[host]*/, int n_stages);
+
+const char* pn_status_string(pn_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAULINET_H */

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) PauliNet walker evaluation.
+
+The compute path is the HIP library libpaulinet.so (built in-tree by
+paper_1909_08423_amd.build); this package only marshals arguments to its C
+ABI.  Importing works without a GPU; every call that launches work needs the
+library and a ROCm device and raises if either is missing.
+"""
+
+from ._lib import (  # noqa: F401
+    PN_PREC_FP64,
+    PN_PREC_NET_BF16,
+    PN_PREC_NET_FP32,
+    PauliNetContext,
+    PauliNetError,
+    library_path,
+    load_library,
+)

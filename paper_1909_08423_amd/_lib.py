@@ -1,0 +1,248 @@
+"""ctypes binding of the C ABI declared in include/paulinet.h.
+
+Argument marshalling only: tensors are passed by device pointer, the HIP
+stream is torch's current stream, and every step of the computation runs in
+the library's kernels.  There is no fallback: a missing library or device is
+an error.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpaulinet.so")
+
+PN_PREC_FP64 = 0
+PN_PREC_NET_FP32 = 1
+PN_PREC_NET_BF16 = 2
+PRECISIONS = {"fp64": PN_PREC_FP64, "fp32": PN_PREC_NET_FP32, "bf16": PN_PREC_NET_BF16}
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_c_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class pn_system_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_nuc", ctypes.c_int32),
+        ("nuc_xyz", _c_dp),
+        ("charge", _c_dp),
+        ("n_up", ctypes.c_int32),
+        ("n_down", ctypes.c_int32),
+        ("n_shell", ctypes.c_int32),
+        ("shell_center", _c_ip),
+        ("shell_l", _c_ip),
+        ("shell_exp", _c_dp),
+        ("n_mo", ctypes.c_int32),
+        ("mo_coeff", _c_dp),
+        ("n_det", ctypes.c_int32),
+        ("det_up", _c_ip),
+        ("det_down", _c_ip),
+        ("ci", _c_dp),
+        ("cusp_radius", ctypes.c_double),
+        ("cusp_nuc_value", _c_dp),
+    ]
+
+
+class pn_net_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_feat", ctypes.c_int32),
+        ("feat_cutoff", ctypes.c_double),
+        ("dim_x", ctypes.c_int32),
+        ("dim_z", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+    ]
+
+
+class PauliNetError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libpaulinet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise PauliNetError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_1909_08423_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.pn_ctx_create.argtypes = [ctypes.POINTER(pn_system_desc), ctypes.POINTER(pn_net_desc),
+                                  ctypes.POINTER(vp)]
+    lib.pn_ctx_create.restype = i32
+    lib.pn_ctx_destroy.argtypes = [vp]
+    lib.pn_ctx_destroy.restype = None
+    lib.pn_param_count.argtypes = [vp]
+    lib.pn_param_count.restype = i64
+    lib.pn_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_workspace_bytes.restype = i32
+    lib.pn_eval.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
+    lib.pn_eval.restype = i32
+    lib.pn_eval_backward.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, ctypes.c_size_t]
+    lib.pn_eval_backward.restype = i32
+    lib.pn_stage_timing.argtypes = [vp, i32]
+    lib.pn_stage_timing.restype = i32
+    lib.pn_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
+    lib.pn_stage_times.restype = i32
+    lib.pn_status_string.argtypes = [i32]
+    lib.pn_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != 0:
+        msg = load_library().pn_status_string(status).decode()
+        raise PauliNetError(f"{what} failed: {msg} (status {status})")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class PauliNetContext:
+    """One system + network shape.  Arrays of the description are copied to
+    the device at construction; parameters and walkers are passed per call."""
+
+    def __init__(self, system, net):
+        lib = load_library()
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            self._keep.append(a)
+            return a.ctypes.data_as(_c_dp if dt == np.float64 else _c_ip)
+
+        s = pn_system_desc()
+        s.n_nuc = int(system.nuc_xyz.shape[0])
+        s.nuc_xyz = arr(system.nuc_xyz, np.float64)
+        s.charge = arr(system.charge, np.float64)
+        s.n_up, s.n_down = int(system.n_up), int(system.n_down)
+        s.n_shell = int(len(system.shell_l))
+        s.shell_center = arr(system.shell_center, np.int32)
+        s.shell_l = arr(system.shell_l, np.int32)
+        s.shell_exp = arr(system.shell_exp, np.float64)
+        s.n_mo = int(system.mo_coeff.shape[1])
+        s.mo_coeff = arr(system.mo_coeff, np.float64)
+        s.n_det = int(system.ci.shape[0])
+        s.det_up = arr(np.asarray(system.det_up).reshape(-1), np.int32)
+        s.det_down = arr(np.asarray(system.det_down).reshape(-1), np.int32)
+        s.ci = arr(system.ci, np.float64)
+        s.cusp_radius = float(system.cusp_radius)
+        s.cusp_nuc_value = (arr(system.cusp_nuc_value, np.float64)
+                            if system.cusp_nuc_value is not None else _c_dp())
+        n = pn_net_desc()
+        n.n_feat, n.feat_cutoff = int(net.n_feat), float(net.feat_cutoff)
+        n.dim_x, n.dim_z, n.n_layers = int(net.dim_x), int(net.dim_z), int(net.n_layers)
+        out = ctypes.c_void_p()
+        _check(lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)), "pn_ctx_create")
+        self._ctx = out
+        self._lib = lib
+        self.n_elec = s.n_up + s.n_down
+        self._ws = {}
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pn_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = ("convert", "geometry_orbitals", "filters", "net_value", "slater_value", "net_tangent",
+              "slater_tangent", "finalize")
+
+    def stage_timing(self, enable=True):
+        _check(self._lib.pn_stage_timing(self._ctx, int(bool(enable))), "pn_stage_timing")
+
+    def stage_times(self):
+        """{stage: (total ms, launches)} since timing was enabled."""
+        n = len(self.STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self._lib.pn_stage_times(self._ctx, ms, cnt, n), "pn_stage_times")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.STAGES)}
+
+    @property
+    def param_count(self):
+        return int(self._lib.pn_param_count(self._ctx))
+
+    def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64):
+        b = ctypes.c_size_t()
+        _check(self._lib.pn_workspace_bytes(self._ctx, int(n_walkers), int(prec), ctypes.byref(b)),
+               "pn_workspace_bytes")
+        return int(b.value)
+
+    def workspace(self, n_walkers, prec, device):
+        import torch
+        need = self.workspace_bytes(n_walkers, prec)
+        key = (str(device),)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    @staticmethod
+    def _stream():
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def eval(self, r, params, prec=PN_PREC_FP64, want_derivs=True, out=None, ws=None):
+        """r: [B, N, 3] float64 CUDA tensor; params: [n_params] float64 CUDA
+        tensor.  Returns dict logabs, sign (and grad, lap, eloc)."""
+        import torch
+        if not (r.is_cuda and params.is_cuda):
+            raise PauliNetError("pn_eval needs device tensors")
+        if r.dtype != torch.float64 or params.dtype != torch.float64:
+            raise PauliNetError("r and params must be float64")
+        r = r.contiguous()
+        params = params.contiguous()
+        B = int(r.shape[0])
+        if r.shape[1] != self.n_elec or r.shape[2] != 3:
+            raise PauliNetError(f"r must be [B, {self.n_elec}, 3]")
+        if params.numel() != self.param_count:
+            raise PauliNetError(f"params must have {self.param_count} entries")
+        dev = r.device
+        if out is None:
+            out = {"logabs": torch.empty(B, dtype=torch.float64, device=dev),
+                   "sign": torch.empty(B, dtype=torch.float64, device=dev)}
+            if want_derivs:
+                out["grad"] = torch.empty(B, self.n_elec, 3, dtype=torch.float64, device=dev)
+                out["lap"] = torch.empty(B, dtype=torch.float64, device=dev)
+                out["eloc"] = torch.empty(B, dtype=torch.float64, device=dev)
+        if ws is None:
+            ws = self.workspace(B, prec, dev)
+        st = self._lib.pn_eval(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
+                               _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out.get("grad")),
+                               _ptr(out.get("lap")), _ptr(out.get("eloc")), _ptr(ws), ws.numel())
+        _check(st, "pn_eval")
+        return out
+
+    def eval_backward(self, r, params, ct_logabs, prec=PN_PREC_FP64, grad_params=None, ws=None):
+        """grad_params += sum_w ct_logabs[w] d ln|psi_w| / d params."""
+        import torch
+        r = r.contiguous()
+        params = params.contiguous()
+        ct_logabs = ct_logabs.contiguous().to(torch.float64)
+        B = int(r.shape[0])
+        if grad_params is None:
+            grad_params = torch.zeros(self.param_count, dtype=torch.float64, device=r.device)
+        if ws is None:
+            ws = self.workspace(B, prec, r.device)
+        st = self._lib.pn_eval_backward(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
+                                        _ptr(ct_logabs), _ptr(grad_params), _ptr(ws), ws.numel())
+        _check(st, "pn_eval_backward")
+        return grad_params

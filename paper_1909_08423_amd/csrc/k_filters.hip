@@ -1,0 +1,131 @@
+// Distance features and filter networks w^(n,c) for every pair, as radial
+// jets (value, derivative / distance, second derivative).
+//
+// e_k(d) = d^2 exp(-d - (d - mu_k)^2 / sigma_k^2)   (Methods, featurisation)
+// w(d)   = ssp(e(d) W1 + b1) W2 + b2                 (two-layer filter, one per
+//                                                     layer n and channel c)
+// With e' and e'' the jets propagate through the first Linear unchanged,
+// through ssp as  y' = ssp'(u) u',  y'' = ssp'(u) u'' + ssp''(u) u'^2,  and
+// through the second Linear unchanged (bias on the value only).  The first
+// derivative is carried divided by d (w'/d), which stays finite as d -> 0.
+//
+// Rows of a block are (walker, pair) of one channel; pairs of a channel are
+// contiguous in the unified pair list (same-spin ee, opposite-spin ee, e-n).
+#include "gemm_lds.h"
+#include "pn_internal.h"
+
+namespace pn {
+namespace {
+
+template <typename TN>
+__global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64_t nw, const double* __restrict__ r,
+                                                      const TN* __restrict__ P, ParamLayout pl, TN* __restrict__ filt,
+                                                      int PT, int n_same, bool bf16) {
+  extern __shared__ __align__(16) char smem[];
+  const int layer = blockIdx.y / 3, ch = blockIdx.y % 3;
+  const int p_lo = ch == 0 ? 0 : (ch == 1 ? n_same : d.n_ee);
+  const int p_hi = ch == 0 ? n_same : (ch == 1 ? d.n_ee : d.n_pairs);
+  const int np = p_hi - p_lo;
+  const int64_t nrows = nw * np;
+  const int64_t row0 = (int64_t)blockIdx.x * PT;
+  if (np == 0 || row0 >= nrows) return;
+  const int rows = (int)min((int64_t)PT, nrows - row0);
+  const int K = d.K, DZ = d.DZ;
+  TN* E = reinterpret_cast<TN*>(smem);         // [3][PT][K]
+  TN* U = E + 3 * PT * K;                      // [3][PT][DZ]
+  double* dd = reinterpret_cast<double*>(U + 3 * PT * DZ);  // [PT]
+
+  // --- distances ---
+  for (int q = threadIdx.x; q < rows; q += blockDim.x) {
+    int64_t g = row0 + q;
+    int64_t w = g / np;
+    int p = p_lo + (int)(g % np);
+    const double* rw = r + w * d.N * 3;
+    double x, y, z;
+    if (p < d.n_ee) {
+      int i = t.pair_ij[2 * p], j = t.pair_ij[2 * p + 1];
+      x = rw[3 * i] - rw[3 * j];
+      y = rw[3 * i + 1] - rw[3 * j + 1];
+      z = rw[3 * i + 2] - rw[3 * j + 2];
+    } else {
+      int q2 = p - d.n_ee, i = q2 / d.NN, I = q2 % d.NN;
+      x = rw[3 * i] - t.nuc_xyz[3 * I];
+      y = rw[3 * i + 1] - t.nuc_xyz[3 * I + 1];
+      z = rw[3 * i + 2] - t.nuc_xyz[3 * I + 2];
+    }
+    dd[q] = sqrt(x * x + y * y + z * z);
+  }
+  __syncthreads();
+  // --- feature jets (computed in FP64, stored in the network type) ---
+  for (int q = threadIdx.x; q < rows * K; q += blockDim.x) {
+    int row = q / K, k = q % K;
+    double dv = dd[row];
+    double dm = dv - t.feat_mu[k], s = t.feat_sig2inv[k];
+    double eg = exp(-dv - dm * dm * s);
+    double g1 = -1.0 - 2.0 * dm * s, g2 = -2.0 * s;
+    E[(0 * PT + row) * K + k] = (TN)(dv * dv * eg);
+    E[(1 * PT + row) * K + k] = (TN)((2.0 + dv * g1) * eg);                              // e'/d
+    E[(2 * PT + row) * K + k] = (TN)((2.0 + 4.0 * dv * g1 + dv * dv * (g1 * g1 + g2)) * eg);  // e''
+  }
+  for (int q = rows + threadIdx.x; q < PT; q += blockDim.x) dd[q] = 1.0;
+  __syncthreads();
+  const ParamLayout::Layer& Lp = pl.layer[layer];
+  // --- first Linear on all three jet rows; rows beyond `rows` are garbage-free zeros ---
+  for (int jet = 0; jet < 3; ++jet)
+    gemm_xw<TN>(E + jet * PT * K, K, rows, K, P + Lp.w1W[ch], DZ, U + jet * PT * DZ, DZ, false, bf16);
+  __syncthreads();
+  // --- ssp jets, in place; bias on the value ---
+  for (int q = threadIdx.x; q < rows * DZ; q += blockDim.x) {
+    int row = q / DZ, z = q % DZ;
+    TN u = U[row * DZ + z] + P[Lp.w1b[ch] + z];
+    TN ud = U[(PT + row) * DZ + z];
+    TN u2 = U[(2 * PT + row) * DZ + z];
+    TN sg = sigmoid_d(u);
+    TN dv = (TN)dd[row];
+    TN up = dv * ud;
+    U[row * DZ + z] = ssp(u);
+    U[(PT + row) * DZ + z] = sg * ud;
+    U[(2 * PT + row) * DZ + z] = sg * u2 + sg * (TN(1) - sg) * up * up;
+  }
+  __syncthreads();
+  // --- second Linear, written straight to global as [walker][layer][jet][pair][DZ] ---
+  const int64_t lstride = (int64_t)3 * d.n_pairs * DZ;
+  for (int jet = 0; jet < 3; ++jet) {
+    const TN* X = U + jet * PT * DZ;
+    const TN* W = P + Lp.w2W[ch];
+    for (int q = threadIdx.x; q < rows * DZ; q += blockDim.x) {
+      int row = q / DZ, o = q % DZ;
+      TN acc = jet == 0 ? P[Lp.w2b[ch] + o] : TN(0);
+      const TN* xr = X + row * DZ;
+      for (int k = 0; k < DZ; ++k) acc += maybe_bf16(xr[k], bf16) * maybe_bf16(W[k * DZ + o], bf16);
+      int64_t g = row0 + row;
+      int64_t w = g / np;
+      int p = p_lo + (int)(g % np);
+      filt[w * (int64_t)d.L * lstride + layer * lstride + ((int64_t)jet * d.n_pairs + p) * DZ + o] = acc;
+    }
+  }
+}
+
+}  // namespace
+
+template <typename TN>
+void launch_filters(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                    const WsLayout& L, bool bf16) {
+  const Dims& d = c->d;
+  const int PT = L.filt_rows;
+  int n_same = 0;
+  // same-spin ee pairs: n_up(n_up-1)/2 + n_dn(n_dn-1)/2
+  n_same = d.n_up * (d.n_up - 1) / 2 + d.n_dn * (d.n_dn - 1) / 2;
+  int64_t max_np = std::max<int64_t>(std::max(n_same, d.n_ee - n_same), (int64_t)d.N * d.NN);
+  int64_t nbx = (nw * max_np + PT - 1) / PT;
+  size_t lds = (size_t)3 * PT * (d.K + d.DZ) * sizeof(TN) + PT * sizeof(double);
+  hipLaunchKernelGGL(k_filters<TN>, dim3((unsigned)nbx, 3 * d.L), dim3(kThreads), lds, s, d, c->t, nw, r, P,
+                     c->pl, reinterpret_cast<TN*>(ws + L.filt), PT, n_same, bf16);
+}
+
+template void launch_filters<double>(const pn_ctx*, hipStream_t, int64_t, const double*, const double*, char*,
+                                     const WsLayout&, bool);
+template void launch_filters<float>(const pn_ctx*, hipStream_t, int64_t, const double*, const float*, char*,
+                                    const WsLayout&, bool);
+
+}  // namespace pn

@@ -1,0 +1,609 @@
+// Host side of the C ABI: context creation (validation, pair and
+// determinant tables, nuclear-cusp polynomials), workspace planning and the
+// launch sequence of the walker-evaluation path.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pn_internal.h"
+
+namespace pn {
+
+template <typename TN>
+size_t tangent_lds_bytes(const Dims& d, int T);
+template <typename TN>
+size_t value_lds_bytes(const Dims& d, int wpb);
+size_t slater_tangent_lds_bytes(const Dims& d, int T);
+void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
+                     bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params);
+size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kWsBudget = size_t(6) << 30;  // walker tiles keep the workspace below ~6 GiB
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr bool kBackwardReady = false;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+ParamLayout make_layout(const Dims& d) {
+  ParamLayout pl{};
+  int64_t off = 0;
+  auto take = [&](int64_t n) {
+    int64_t o = off;
+    off += n;
+    return o;
+  };
+  const int64_t K = d.K, X = d.DX, Z = d.DZ;
+  pl.x0 = take(X);
+  pl.Y = take((int64_t)d.NN * Z);
+  for (int n = 0; n < d.L; ++n) {
+    ParamLayout::Layer& Lp = pl.layer[n];
+    for (int c = 0; c < 3; ++c) {
+      Lp.w1W[c] = take(K * Z);
+      Lp.w1b[c] = take(Z);
+      Lp.w2W[c] = take(Z * Z);
+      Lp.w2b[c] = take(Z);
+    }
+    Lp.hW = take(X * Z);
+    Lp.hb = take(Z);
+    for (int c = 0; c < 3; ++c) {
+      Lp.gW[c] = take(Z * X);
+      Lp.gb[c] = take(X);
+    }
+  }
+  pl.eW1 = take(X * X);
+  pl.eb1 = take(X);
+  pl.eW2 = take(X * X);
+  pl.eb2 = take(X);
+  pl.eW3 = take(X);
+  pl.eb3 = take(1);
+  pl.kW1 = take(X * X);
+  pl.kb1 = take(X);
+  pl.kW2 = take(X * X);
+  pl.kb2 = take(X);
+  pl.kW3 = take(X * d.M);
+  pl.kb3 = take(d.M);
+  pl.total = off;
+  return pl;
+}
+
+template <typename T>
+T* dev_copy(const std::vector<T>& v, hipError_t* err) {
+  T* p = nullptr;
+  size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) *err = e;
+  return p;
+}
+
+// Solve the 3x3 system M a = b by Gaussian elimination with partial pivoting.
+bool solve3(double M[3][3], double b[3], double x[3]) {
+  int idx[3] = {0, 1, 2};
+  for (int c = 0; c < 3; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 3; ++r)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (M[piv][c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < 3; ++k) std::swap(M[c][k], M[piv][k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < 3; ++r) {
+      double l = M[r][c] / M[c][c];
+      for (int k = c; k < 3; ++k) M[r][k] -= l * M[c][k];
+      b[r] -= l * b[c];
+    }
+  }
+  (void)idx;
+  for (int r = 2; r >= 0; --r) {
+    double v = b[r];
+    for (int k = r + 1; k < 3; ++k) v -= M[r][k] * x[k];
+    x[r] = v / M[r][r];
+  }
+  return true;
+}
+
+}  // namespace
+
+// Workspace plan for `nw` walkers; net_bytes = sizeof of the network type.
+WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
+  const Dims& d = c->d;
+  const bool fp64 = prec == PN_PREC_FP64;
+  const size_t tn = fp64 ? sizeof(double) : sizeof(float);
+  WsLayout L{};
+  // chunking of the 3N coordinates for the tangent pass
+  const size_t budget = fp64 ? 84 * 1024 : 66 * 1024;
+  const int ncoord = 3 * d.N;
+  L.T = 1;
+  for (int nc = 1; nc <= ncoord; ++nc) {
+    int T = (ncoord + nc - 1) / nc;
+    size_t lds = fp64 ? tangent_lds_bytes<double>(d, T) : tangent_lds_bytes<float>(d, T);
+    if (lds <= budget || T == 1) {
+      L.T = T;
+      break;
+    }
+  }
+  L.n_chunks = (ncoord + L.T - 1) / L.T;
+  L.lds_tangent = fp64 ? tangent_lds_bytes<double>(d, L.T) : tangent_lds_bytes<float>(d, L.T);
+  L.wpb_value = std::max(1, 64 / d.N);
+  while (L.wpb_value > 1 &&
+         (fp64 ? value_lds_bytes<double>(d, L.wpb_value) : value_lds_bytes<float>(d, L.wpb_value)) > 64 * 1024)
+    L.wpb_value /= 2;
+  L.lds_value = fp64 ? value_lds_bytes<double>(d, L.wpb_value) : value_lds_bytes<float>(d, L.wpb_value);
+  L.filt_rows = 64;
+  while (L.filt_rows > 8 && (size_t)3 * L.filt_rows * (d.K + d.DZ) * tn + L.filt_rows * 8 > 64 * 1024)
+    L.filt_rows /= 2;
+  L.lds_filter = (size_t)3 * L.filt_rows * (d.K + d.DZ) * tn + L.filt_rows * 8;
+
+  const int N = d.N, M = d.M, P = d.P, Tp = L.T + 1;
+  const size_t gsz = (size_t)d.n_up * d.n_up + (size_t)d.n_dn * d.n_dn;
+  // bytes per walker of every tile-sized region
+  auto per_walker = [&](bool with_bwd) {
+    size_t b = 0;
+    b += align_up(kGeoStride(N) * 8);
+    b += (size_t)N * M * 7 * 8;
+    b += (size_t)d.L * 3 * d.n_pairs * d.DZ * tn;
+    b += (size_t)d.L * N * d.DZ * tn;
+    b += (size_t)4 * N * d.DX * tn + 4 * d.DX * tn;
+    b += (size_t)N * M * 8 + 8;
+    b += (size_t)P * gsz * 8 + (size_t)P * 4 * 8 + (size_t)P * 8 + 8;
+    b += (size_t)L.n_chunks * N * Tp * M * 8 + (size_t)L.n_chunks * Tp * 8 + (size_t)L.n_chunks * 2 * 8;
+    b += (size_t)N * 3 * 8;
+    if (with_bwd) b += (size_t)(d.L + 1) * N * d.DX * tn;
+    return b;
+  };
+  size_t pw = per_walker(backward);
+  int64_t tile = (int64_t)std::max<size_t>(256, kWsBudget / std::max<size_t>(pw, 1));
+  tile = std::min<int64_t>(tile, std::max<int64_t>(nw, 1));
+  L.tile = tile;
+  size_t off = 0;
+  auto region = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.params_net = region(fp64 ? 0 : (size_t)c->pl.total * sizeof(float));
+  L.geo = region((size_t)tile * kGeoStride(N) * 8);
+  L.phi = region((size_t)tile * N * M * 7 * 8);
+  L.filt = region((size_t)tile * d.L * 3 * d.n_pairs * d.DZ * tn);
+  L.hval = region((size_t)tile * d.L * N * d.DZ * tn);
+  L.kcoef = region((size_t)tile * 4 * N * d.DX * tn);
+  L.ecoef = region((size_t)tile * 4 * d.DX * tn);
+  L.fval = region((size_t)tile * N * M * 8);
+  L.jval = region((size_t)tile * 8);
+  L.ginv = region((size_t)tile * P * gsz * 8);
+  L.ldet = region((size_t)tile * P * 4 * 8);
+  L.wdet = region((size_t)tile * P * 8);
+  L.ldpsi = region((size_t)tile * 8);
+  L.ftan = region((size_t)tile * L.n_chunks * N * Tp * M * 8);
+  L.jtan = region((size_t)tile * L.n_chunks * Tp * 8);
+  L.partial = region((size_t)tile * L.n_chunks * 2 * 8);
+  // grad scratch for calls that want lap/eloc without grad
+  L.adj = region((size_t)tile * N * 3 * 8);
+  L.xval = 0;
+  L.gpart = 0;
+  if (backward) {
+    L.xval = region((size_t)tile * (d.L + 1) * N * d.DX * tn);
+    L.gpart = region(backward_scratch_bytes(c, tile, !fp64));
+  }
+  L.total = off;
+  return L;
+}
+
+// ---- optional stage timing ----
+namespace {
+void harvest_set(pn_ctx::Timing* T, int set) {
+  for (int k = 0; k < pn_ctx::Timing::kStages; ++k) {
+    if (!T->rec[set][k]) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(T->ev[set][k][1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, T->ev[set][k][0], T->ev[set][k][1]) == hipSuccess) {
+      T->ms[k] += ms;
+      T->cnt[k] += 1;
+    }
+    T->rec[set][k] = false;
+  }
+}
+struct StageClock {
+  pn_ctx::Timing* T;
+  hipStream_t s;
+  StageClock(const pn_ctx* c, hipStream_t st) : T(c->timing && c->timing->on ? c->timing : nullptr), s(st) {
+    if (T) harvest_set(T, T->cur);
+  }
+  void begin(int k) {
+    if (T) (void)hipEventRecord(T->ev[T->cur][k][0], s);
+  }
+  void end(int k) {
+    if (!T) return;
+    (void)hipEventRecord(T->ev[T->cur][k][1], s);
+    T->rec[T->cur][k] = true;
+  }
+  void next_set() {
+    if (!T) return;
+    T->cur = (T->cur + 1) % pn_ctx::Timing::kSets;
+    harvest_set(T, T->cur);
+  }
+};
+}  // namespace
+
+}  // namespace pn
+
+using namespace pn;
+
+extern "C" {
+
+const char* pn_status_string(pn_status s) {
+  switch (s) {
+    case PN_OK: return "ok";
+    case PN_ERR_INVALID_ARG: return "invalid argument";
+    case PN_ERR_UNSUPPORTED_SHAPE: return "unsupported shape";
+    case PN_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case PN_ERR_DEVICE: return "device error";
+    case PN_ERR_BUDGET: return "over budget";
+  }
+  return "unknown status";
+}
+
+pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ctx** out) {
+  if (!out) return PN_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!sys || !net) return PN_ERR_INVALID_ARG;
+  if (sys->n_nuc < 1 || !sys->nuc_xyz || !sys->charge || sys->n_shell < 1 || !sys->shell_center ||
+      !sys->shell_l || !sys->shell_exp || sys->n_mo < 1 || !sys->mo_coeff || sys->n_det < 1 || !sys->ci ||
+      sys->n_up < 0 || sys->n_down < 0 || sys->n_up + sys->n_down < 1 || (sys->n_up > 0 && !sys->det_up) ||
+      (sys->n_down > 0 && !sys->det_down) || !(sys->cusp_radius >= 0))
+    return PN_ERR_INVALID_ARG;
+  if (net->n_feat < 1 || net->dim_x < 1 || net->dim_z < 1 || net->n_layers < 1 || !(net->feat_cutoff > 0))
+    return PN_ERR_INVALID_ARG;
+  const int N = sys->n_up + sys->n_down;
+  if (sys->n_up > kMaxSpin || sys->n_down > kMaxSpin || N > kMaxElec || sys->n_det > kMaxDet ||
+      net->dim_x > 128 || net->dim_z > 128 || net->n_feat > 64 || net->n_layers > kMaxLayers ||
+      sys->n_nuc > kMaxNuc || sys->n_mo > net->dim_x)
+    return PN_ERR_UNSUPPORTED_SHAPE;
+  int NB = 0;
+  for (int s = 0; s < sys->n_shell; ++s) {
+    if (sys->shell_l[s] < 0 || sys->shell_l[s] > 1) return PN_ERR_UNSUPPORTED_SHAPE;
+    if (sys->shell_center[s] < 0 || sys->shell_center[s] >= sys->n_nuc || !(sys->shell_exp[s] > 0))
+      return PN_ERR_INVALID_ARG;
+    NB += 2 * sys->shell_l[s] + 1;
+  }
+  const int M = sys->n_mo, P = sys->n_det, NN = sys->n_nuc;
+  for (int p = 0; p < P; ++p) {
+    for (int k = 0; k < sys->n_up; ++k)
+      if (sys->det_up[p * sys->n_up + k] < 0 || sys->det_up[p * sys->n_up + k] >= M) return PN_ERR_INVALID_ARG;
+    for (int k = 0; k < sys->n_down; ++k)
+      if (sys->det_down[p * sys->n_down + k] < 0 || sys->det_down[p * sys->n_down + k] >= M)
+        return PN_ERR_INVALID_ARG;
+  }
+
+  pn_ctx* c = new pn_ctx();
+  Dims& d = c->d;
+  d.N = N;
+  d.n_up = sys->n_up;
+  d.n_dn = sys->n_down;
+  d.NN = NN;
+  d.NB = NB;
+  d.M = M;
+  d.P = P;
+  d.K = net->n_feat;
+  d.DX = net->dim_x;
+  d.DZ = net->dim_z;
+  d.L = net->n_layers;
+  d.n_ee = N * (N - 1) / 2;
+  d.n_pairs = d.n_ee + N * NN;
+  d.n_shell = sys->n_shell;
+  d.feat_rc = net->feat_cutoff;
+  d.cusp_rc = sys->cusp_radius;
+  double vnn = 0.0;
+  for (int I = 0; I < NN; ++I)
+    for (int J = I + 1; J < NN; ++J) {
+      double dx = sys->nuc_xyz[3 * I] - sys->nuc_xyz[3 * J], dy = sys->nuc_xyz[3 * I + 1] - sys->nuc_xyz[3 * J + 1],
+             dz = sys->nuc_xyz[3 * I + 2] - sys->nuc_xyz[3 * J + 2];
+      vnn += sys->charge[I] * sys->charge[J] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  d.v_nn = vnn;
+  c->pl = make_layout(d);
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+
+  // ---- host tables ----
+  std::vector<double> nuc(sys->nuc_xyz, sys->nuc_xyz + 3 * NN), chg(sys->charge, sys->charge + NN);
+  std::vector<int> sc(sys->shell_center, sys->shell_center + d.n_shell), sl(sys->shell_l, sys->shell_l + d.n_shell);
+  std::vector<double> se(sys->shell_exp, sys->shell_exp + d.n_shell), sn(d.n_shell);
+  std::vector<int> sfirst(d.n_shell);
+  int b = 0;
+  for (int s = 0; s < d.n_shell; ++s) {
+    double a = se[s];
+    sn[s] = sl[s] == 0 ? pow(2.0 * a / M_PI, 0.75) : pow(128.0 * pow(a, 5) / pow(M_PI, 3), 0.25);
+    sfirst[s] = b;
+    b += 2 * sl[s] + 1;
+  }
+  std::vector<double> mo(sys->mo_coeff, sys->mo_coeff + (size_t)NB * M);
+  std::vector<int> du(sys->det_up, sys->det_up + (size_t)P * d.n_up), dd(sys->det_down, sys->det_down + (size_t)P * d.n_dn);
+  std::vector<double> clog(P), csign(P);
+  for (int p = 0; p < P; ++p) {
+    clog[p] = log(fabs(sys->ci[p]));
+    csign[p] = sys->ci[p] > 0 ? 1.0 : (sys->ci[p] < 0 ? -1.0 : 0.0);
+  }
+  // s functions grouped by nucleus
+  std::vector<int> s_first(NN + 1, 0), s_basis;
+  std::vector<double> s_exp, s_norm;
+  for (int I = 0; I < NN; ++I) {
+    s_first[I] = (int)s_basis.size();
+    for (int s = 0; s < d.n_shell; ++s)
+      if (sc[s] == I && sl[s] == 0) {
+        s_basis.push_back(sfirst[s]);
+        s_exp.push_back(se[s]);
+        s_norm.push_back(sn[s]);
+      }
+  }
+  s_first[NN] = (int)s_basis.size();
+  // nuclear cusp polynomials (Ma et al. scheme, nucleus value as input)
+  std::vector<int> cusp_on((size_t)NN * M, 0);
+  std::vector<double> cusp_sign((size_t)NN * M, 0.0), cusp_alpha((size_t)NN * M * 5, 0.0);
+  int n_on = 0;
+  if (d.cusp_rc > 0) {
+    const double rc = d.cusp_rc;
+    for (int I = 0; I < NN; ++I) {
+      if (s_first[I] == s_first[I + 1]) continue;
+      for (int mu = 0; mu < M; ++mu) {
+        // uncorrected orbital at the nucleus
+        double phi0 = 0.0;
+        for (int s = 0; s < d.n_shell; ++s) {
+          double dx = nuc[3 * I] - nuc[3 * sc[s]], dy = nuc[3 * I + 1] - nuc[3 * sc[s] + 1],
+                 dz = nuc[3 * I + 2] - nuc[3 * sc[s] + 2];
+          double g = sn[s] * exp(-se[s] * (dx * dx + dy * dy + dz * dz));
+          if (sl[s] == 0) {
+            phi0 += mo[(size_t)sfirst[s] * M + mu] * g;
+          } else {
+            double x[3] = {dx, dy, dz};
+            for (int k = 0; k < 3; ++k) phi0 += mo[(size_t)(sfirst[s] + k) * M + mu] * x[k] * g;
+          }
+        }
+        double s0u = 0.0, sv = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int k = s_first[I]; k < s_first[I + 1]; ++k) {
+          double cn = mo[(size_t)s_basis[k] * M + mu] * s_norm[k], a = s_exp[k];
+          double e = exp(-a * rc * rc);
+          s0u += cn;
+          sv += cn * e;
+          s1 += cn * (-2.0 * a * rc) * e;
+          s2 += cn * (4.0 * a * a * rc * rc - 2.0 * a) * e;
+        }
+        double s0 = sys->cusp_nuc_value ? sys->cusp_nuc_value[(size_t)I * M + mu] : s0u;
+        if (s0 == 0.0 || !(sv * s0 > 0.0)) continue;
+        double eta0 = phi0 - s0u;
+        double a0 = log(fabs(s0));
+        double a1 = -sys->charge[I] * (eta0 + s0) / s0;
+        double X1 = log(fabs(sv)), X2 = s1 / sv, X3 = s2 / sv - X2 * X2;
+        double Mm[3][3] = {{rc * rc, rc * rc * rc, rc * rc * rc * rc},
+                           {2 * rc, 3 * rc * rc, 4 * rc * rc * rc},
+                           {2.0, 6 * rc, 12 * rc * rc}};
+        double rhs[3] = {X1 - a0 - a1 * rc, X2 - a1, X3}, sol[3];
+        if (!solve3(Mm, rhs, sol)) continue;
+        size_t q = (size_t)I * M + mu;
+        cusp_on[q] = 1;
+        cusp_sign[q] = s0 > 0 ? 1.0 : -1.0;
+        cusp_alpha[5 * q + 0] = a0;
+        cusp_alpha[5 * q + 1] = a1;
+        cusp_alpha[5 * q + 2] = sol[0];
+        cusp_alpha[5 * q + 3] = sol[1];
+        cusp_alpha[5 * q + 4] = sol[2];
+        ++n_on;
+      }
+    }
+  }
+  c->n_cusp_on = n_on;
+  // features
+  std::vector<double> fmu(d.K), fs(d.K);
+  for (int k = 0; k < d.K; ++k) {
+    double q = d.K > 1 ? double(k) / double(d.K - 1) : 0.0;
+    fmu[k] = d.feat_rc * q * q;
+    double sg = (1.0 + d.feat_rc * q) / 7.0;
+    fs[k] = 1.0 / (sg * sg);
+  }
+  // pairs: same-spin ee (i<j), then opposite-spin ee, then e-n
+  std::vector<int> pij, pidx((size_t)N * N, -1);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        bool same = (i < d.n_up) == (j < d.n_up);
+        if (same != (pass == 0)) continue;
+        int p = (int)pij.size() / 2;
+        pij.push_back(i);
+        pij.push_back(j);
+        pidx[(size_t)i * N + j] = p;
+        pidx[(size_t)j * N + i] = p;
+      }
+
+  hipError_t err = hipSuccess;
+  DevTables& t = c->t;
+  t.nuc_xyz = dev_copy(nuc, &err);
+  t.charge = dev_copy(chg, &err);
+  t.shell_center = dev_copy(sc, &err);
+  t.shell_l = dev_copy(sl, &err);
+  t.shell_exp = dev_copy(se, &err);
+  t.shell_norm = dev_copy(sn, &err);
+  t.shell_first = dev_copy(sfirst, &err);
+  t.mo = dev_copy(mo, &err);
+  t.det_up = dev_copy(du, &err);
+  t.det_dn = dev_copy(dd, &err);
+  t.ci_log = dev_copy(clog, &err);
+  t.ci_sign = dev_copy(csign, &err);
+  t.cusp_on = dev_copy(cusp_on, &err);
+  t.cusp_sign = dev_copy(cusp_sign, &err);
+  t.cusp_alpha = dev_copy(cusp_alpha, &err);
+  t.s_first = dev_copy(s_first, &err);
+  t.s_basis = dev_copy(s_basis, &err);
+  t.s_exp = dev_copy(s_exp, &err);
+  t.s_norm = dev_copy(s_norm, &err);
+  t.feat_mu = dev_copy(fmu, &err);
+  t.feat_sig2inv = dev_copy(fs, &err);
+  t.pair_ij = dev_copy(pij, &err);
+  t.pair_index = dev_copy(pidx, &err);
+  if (err != hipSuccess) {
+    pn_ctx_destroy(c);
+    return PN_ERR_DEVICE;
+  }
+  *out = c;
+  return PN_OK;
+}
+
+void pn_ctx_destroy(pn_ctx* c) {
+  if (!c) return;
+  if (c->timing) {
+    for (int a = 0; a < pn_ctx::Timing::kSets; ++a)
+      for (int k = 0; k < pn_ctx::Timing::kStages; ++k)
+        for (int e = 0; e < 2; ++e)
+          if (c->timing->ev[a][k][e]) (void)hipEventDestroy(c->timing->ev[a][k][e]);
+    delete c->timing;
+  }
+  void* ptrs[] = {c->t.nuc_xyz, c->t.charge, c->t.shell_center, c->t.shell_l, c->t.shell_exp, c->t.shell_norm,
+                  c->t.shell_first, c->t.mo, c->t.det_up, c->t.det_dn, c->t.ci_log, c->t.ci_sign, c->t.cusp_on,
+                  c->t.cusp_sign, c->t.cusp_alpha, c->t.s_first, c->t.s_basis, c->t.s_exp, c->t.s_norm,
+                  c->t.feat_mu, c->t.feat_sig2inv, c->t.pair_ij, c->t.pair_index};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+int64_t pn_param_count(const pn_ctx* c) { return c ? c->pl.total : -1; }
+
+pn_status pn_workspace_bytes(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
+  if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  WsLayout L = plan(c, nw, prec, true);
+  *bytes = L.total;
+  return PN_OK;
+}
+
+pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                  pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc, void* ws,
+                  size_t ws_bytes) {
+  if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  if (nw == 0) return PN_OK;
+  if (!r || !params || !logabs || !sign || !ws) return PN_ERR_INVALID_ARG;
+  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
+  WsLayout L = plan(c, nw, prec, false);
+  if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
+  if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
+  char* base = static_cast<char*>(ws);
+  const bool derivs = grad || lap || eloc;
+  const Dims& d = c->d;
+  const void* P = params;
+  StageClock clk(c, s);
+  if (!fp64) {
+    clk.begin(0);
+    launch_convert_params(s, c->pl.total, params, reinterpret_cast<float*>(base + L.params_net));
+    clk.end(0);
+    P = base + L.params_net;
+  }
+  for (int64_t w0 = 0; w0 < nw; w0 += L.tile) {
+    const int64_t n = std::min<int64_t>(L.tile, nw - w0);
+    const double* rt = r + w0 * d.N * 3;
+    clk.begin(1);
+    launch_geometry_orbitals(c, s, n, rt, base, L);
+    clk.end(1);
+    if (fp64) {
+      clk.begin(2);
+      launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
+      clk.end(2);
+      clk.begin(3);
+      launch_net_value<double>(c, s, n, static_cast<const double*>(P), base, L, false);
+      clk.end(3);
+    } else {
+      clk.begin(2);
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      clk.end(2);
+      clk.begin(3);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+      clk.end(3);
+    }
+    clk.begin(4);
+    launch_slater_value(c, s, n, base, L, logabs + w0, sign + w0);
+    clk.end(4);
+    if (derivs) {
+      clk.begin(5);
+      if (fp64)
+        launch_net_tangent<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
+      else
+        launch_net_tangent<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      clk.end(5);
+      double* g = grad ? grad + w0 * d.N * 3 : reinterpret_cast<double*>(base + L.adj);
+      clk.begin(6);
+      launch_slater_tangent(c, s, n, rt, base, L, g);
+      clk.end(6);
+      clk.begin(7);
+      launch_finalize(c, s, n, base, L, g, lap ? lap + w0 : nullptr, eloc ? eloc + w0 : nullptr);
+      clk.end(7);
+    }
+    clk.next_set();
+  }
+  if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
+  return PN_OK;
+}
+
+pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                           pn_precision prec, const double* ct_logabs, double* grad_params, void* ws,
+                           size_t ws_bytes) {
+  if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  if (nw == 0) return PN_OK;
+  if (!r || !params || !ct_logabs || !grad_params || !ws) return PN_ERR_INVALID_ARG;
+  if (!kBackwardReady) return PN_ERR_UNSUPPORTED_SHAPE;
+  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
+  WsLayout L = plan(c, nw, prec, true);
+  if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
+  char* base = static_cast<char*>(ws);
+  const void* P = params;
+  if (!fp64) {
+    launch_convert_params(s, c->pl.total, params, reinterpret_cast<float*>(base + L.params_net));
+    P = base + L.params_net;
+  }
+  launch_backward(c, s, nw, r, P, !fp64, bf16, ct_logabs, base, L, grad_params);
+  if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
+  return PN_OK;
+}
+
+pn_status pn_stage_timing(pn_ctx* c, int enable) {
+  if (!c) return PN_ERR_INVALID_ARG;
+  if (enable) {
+    if (!c->timing) {
+      c->timing = new pn_ctx::Timing();
+      for (int a = 0; a < pn_ctx::Timing::kSets; ++a)
+        for (int k = 0; k < pn_ctx::Timing::kStages; ++k)
+          for (int e = 0; e < 2; ++e)
+            if (hipEventCreate(&c->timing->ev[a][k][e]) != hipSuccess) return PN_ERR_DEVICE;
+    }
+    for (int k = 0; k < pn_ctx::Timing::kStages; ++k) {
+      c->timing->ms[k] = 0;
+      c->timing->cnt[k] = 0;
+    }
+    c->timing->on = true;
+  } else if (c->timing) {
+    c->timing->on = false;
+  }
+  return PN_OK;
+}
+
+pn_status pn_stage_times(pn_ctx* c, double* ms, int64_t* cnt, int n) {
+  if (!c || !ms || !cnt || n < PN_N_STAGES) return PN_ERR_INVALID_ARG;
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0;
+    cnt[k] = 0;
+  }
+  if (!c->timing) return PN_OK;
+  for (int a = 0; a < pn_ctx::Timing::kSets; ++a) harvest_set(c->timing, a);
+  for (int k = 0; k < PN_N_STAGES; ++k) {
+    ms[k] = c->timing->ms[k];
+    cnt[k] = c->timing->cnt[k];
+  }
+  return PN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Internal definitions shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/paulinet.h"
+
+namespace pn {
+
+constexpr int kMaxLayers = 8;
+constexpr int kMaxNuc = 64;
+constexpr int kMaxElec = 64;
+constexpr int kMaxSpin = 32;
+constexpr int kMaxDet = 64;
+constexpr int kThreads = 256;
+
+// Offsets (in elements) of every tensor inside the flat parameter blob.
+struct ParamLayout {
+  int64_t x0, Y;
+  struct Layer {
+    int64_t w1W[3], w1b[3], w2W[3], w2b[3];
+    int64_t hW, hb;
+    int64_t gW[3], gb[3];
+  } layer[kMaxLayers];
+  int64_t eW1, eb1, eW2, eb2, eW3, eb3;
+  int64_t kW1, kb1, kW2, kb2, kW3, kb3;
+  int64_t total;
+};
+
+// Problem sizes, passed by value to every kernel.
+struct Dims {
+  int N, n_up, n_dn, NN, NB, M, P;
+  int K, DX, DZ, L;
+  int n_ee;      // N (N - 1) / 2 electron pairs i < j
+  int n_pairs;   // n_ee + N * NN
+  int n_shell;
+  double feat_rc;
+  double cusp_rc;
+  double v_nn;   // nuclear repulsion, a constant of the geometry
+};
+
+// Device-resident copies of the system tables (owned by the context).
+struct DevTables {
+  double* nuc_xyz;     // [NN][3]
+  double* charge;      // [NN]
+  int* shell_center;   // [n_shell]
+  int* shell_l;        // [n_shell]
+  double* shell_exp;   // [n_shell]
+  double* shell_norm;  // [n_shell]
+  int* shell_first;    // [n_shell] first basis index
+  double* mo;          // [NB][M]
+  int* det_up;         // [P][n_up]
+  int* det_dn;         // [P][n_dn]
+  double* ci_log;      // [P] ln|c_p|
+  double* ci_sign;     // [P] sign c_p
+  // nuclear cusp correction, per (nucleus, MO)
+  int* cusp_on;        // [NN][M]
+  double* cusp_sign;   // [NN][M]
+  double* cusp_alpha;  // [NN][M][5]
+  int* s_first;        // [NN+1] CSR offsets into s_basis
+  int* s_basis;        // basis index of each s function, grouped by nucleus
+  double* s_exp;       // exponent of each s function (same order)
+  double* s_norm;      // normalisation of each s function
+  // distance features
+  double* feat_mu;     // [K]
+  double* feat_sig2inv;// [K] 1 / sigma_k^2
+  // pairs
+  int* pair_ij;        // [n_ee][2] (i < j)
+  int* pair_index;     // [N][N] unified pair index of the ee pair, -1 on the diagonal
+};
+
+// Workspace regions for one walker tile (byte offsets from ws base).
+struct WsLayout {
+  int64_t tile;        // walkers per tile
+  int T;               // coordinates per tangent chunk
+  int n_chunks;
+  int wpb_value;       // walkers per block in the value network kernel
+  size_t lds_tangent;  // dynamic LDS of the tangent kernel
+  size_t lds_value;
+  size_t lds_filter;
+  int filt_rows;       // pairs per block in the filter kernel
+  // offsets
+  size_t params_net;   // converted params (float) when the network is FP32/BF16
+  size_t geo;          // [tile][GEO] V, gamma, then per electron grad(3) + hess diag(3)
+  size_t phi;          // [tile][N][M][7] value, grad(3), d2 diag(3)
+  size_t filt;         // [tile][L][3][n_pairs][DZ]  (w, w'/d, w'')  net type
+  size_t hval;         // [tile][L][N][DZ]                           net type
+  size_t kcoef;        // [tile][2][2][N][DX] (ssp', ssp'') per kappa hidden layer
+  size_t ecoef;        // [tile][2][2][DX]
+  size_t fval;         // [tile][N][M]  double
+  size_t jval;         // [tile]        double
+  size_t ginv;         // [tile][P][n_up*n_up + n_dn*n_dn] inverse matrices
+  size_t ldet;         // [tile][P][2][2] (ln|det|, sign) per spin
+  size_t wdet;         // [tile][P] signed determinant weights
+  size_t ldpsi;        // [tile] ln|psi_d|
+  size_t ftan;         // [tile][n_chunks][N][T+1][M] double
+  size_t jtan;         // [tile][n_chunks][T+1] double
+  size_t partial;      // [tile][n_chunks][2]
+  size_t xval;         // [tile][L+1][N][DX] activations (backward only)
+  size_t adj;          // backward scratch
+  size_t gpart;        // [n_blocks][n_params] per-block parameter gradients
+  size_t total;
+};
+
+constexpr int kGeoStride(int N) { return 4 + 6 * N; }  // V, gamma, lap_gamma, pad, N*(grad3, hess3)
+
+}  // namespace pn
+
+struct pn_ctx {
+  pn::Dims d;
+  pn::ParamLayout pl;
+  pn::DevTables t;
+  int device;
+  int n_cusp_on;
+  // optional per-stage timing (profiling only; not part of the immutable state)
+  struct Timing {
+    static constexpr int kSets = 64, kStages = PN_N_STAGES;
+    bool on = false;
+    hipEvent_t ev[kSets][kStages][2] = {};
+    bool rec[kSets][kStages] = {};
+    int cur = 0;
+    double ms[kStages] = {};
+    int64_t cnt[kStages] = {};
+  };
+  mutable Timing* timing = nullptr;
+};
+
+namespace pn {
+
+// ---------------------------------------------------------------- helpers --
+__device__ __forceinline__ double sigmoid_d(double x) { return 1.0 / (1.0 + exp(-x)); }
+__device__ __forceinline__ float sigmoid_d(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// Shifted softplus ssp(x) = ln(1 + e^x) - ln 2, evaluated stably.
+__device__ __forceinline__ double ssp(double x) {
+  return (x > 0 ? x + log1p(exp(-x)) : log1p(exp(x))) - 0.69314718055994530942;
+}
+__device__ __forceinline__ float ssp(float x) {
+  return (x > 0.f ? x + log1pf(__expf(-x)) : log1pf(__expf(x))) - 0.69314718f;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_param(const T* p, int64_t i) {
+  return p[i];
+}
+
+}  // namespace pn
+
+// Launchers implemented in the kernel translation units.
+namespace pn {
+void launch_geometry_orbitals(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws,
+                              const WsLayout& L);
+template <typename TN>
+void launch_filters(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                    const WsLayout& L, bool bf16);
+template <typename TN>
+void launch_net_value(const pn_ctx* c, hipStream_t s, int64_t nw, const TN* P, char* ws, const WsLayout& L,
+                      bool bf16);
+template <typename TN>
+void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                        const WsLayout& L, bool bf16);
+void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L,
+                         double* logabs, double* sign);
+void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws,
+                           const WsLayout& L, double* grad);
+void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* grad,
+                     double* lap, double* eloc);
+void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst);
+}  // namespace pn

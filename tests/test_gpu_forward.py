@@ -1,0 +1,122 @@
+"""GPU parity of the forward path (ln|psi|, sign, grad, Laplacian, E_loc)
+against the FP64 oracle, through the C ABI.
+
+Oracle values are stored fixtures written by tests/golden/make_oracle_fixtures.py
+(which calls only oracle/).  FP64 bar: per walker
+  |d ln|psi|| <= 1e-6 max(1, |ln|psi||),  ||d grad|| <= 1e-6 max(1, ||grad||),
+  |d lap| and |d E_loc| <= 1e-6 x the scale of the cancelling kinetic terms,
+  signs equal.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import announce, load_fixture, parity_ratios, summarize
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pn():
+    import paper_1909_08423_amd as pn
+    assert torch.cuda.is_available(), "no ROCm device"
+    pn.load_library()
+    return pn
+
+
+def _run(pn, w, walkers, prec, derivs=True):
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    out = ctx.eval(r, th, prec, want_derivs=derivs)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}, ctx
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3, 5])
+def test_fp64_parity_ragged_batch(pn, idx):
+    try:
+        fx = load_fixture(idx)
+    except FileNotFoundError:
+        pytest.skip(f"no oracle fixture for workload {idx}")
+    w = make_config(idx, n_walkers=4)
+    announce(f"fp64 parity workload {idx} B={fx['walkers'].shape[0]}")
+    out, _ = _run(pn, w, fx["walkers"], pn.PN_PREC_FP64)
+    np.testing.assert_array_equal(out["sign"], fx["sign"])
+    rat = parity_ratios(out, fx)
+    for k, v in rat.items():
+        assert v.max() <= TOL64, f"{k}: worst {v.max():.3e} at walker {int(v.argmax())}; {summarize(rat)}"
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_fp64_parity_full_batch_sample(pn, idx):
+    """Full-size batch in the benchmark's launch configuration; the oracle
+    values of a sample of walkers are compared one by one."""
+    fx = load_fixture(idx)
+    w = make_config(idx)
+    announce(f"fp64 full batch workload {idx} B={w.walkers.shape[0]}")
+    out, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64)
+    s = fx["full_sample"]
+    sub = {k: out[k][s] for k in out}
+    ref = {k: fx["full_" + k] for k in ("logabs", "sign", "grad", "lap", "eloc")}
+    np.testing.assert_array_equal(sub["sign"], ref["sign"])
+    rat = parity_ratios(sub, ref)
+    for k, v in rat.items():
+        assert v.max() <= TOL64, f"{k}: worst {v.max():.3e}; {summarize(rat)}"
+    assert np.all(np.isfinite(out["eloc"]))
+
+
+def test_value_only_matches_full(pn):
+    w = make_config(2, n_walkers=100)
+    announce("value-only vs full, workload 2")
+    a, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64, derivs=False)
+    b, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64, derivs=True)
+    np.testing.assert_array_equal(a["logabs"], b["logabs"])
+    np.testing.assert_array_equal(a["sign"], b["sign"])
+
+
+def test_deterministic_bits(pn):
+    w = make_config(3, n_walkers=300)
+    announce("determinism, workload 3")
+    a, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64)
+    b, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_antisymmetry_on_gpu(pn):
+    """Same-spin exchange: sign flips, ln|psi|, lap and E_loc unchanged,
+    gradient permuted (Results, eq. "antisymmetry")."""
+    w = make_config(2, n_walkers=64)
+    announce("antisymmetry, workload 2")
+    a, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64)
+    rs = w.walkers.copy()
+    rs[:, [1, 4]] = rs[:, [4, 1]]
+    b, _ = _run(pn, w, rs, pn.PN_PREC_FP64)
+    np.testing.assert_array_equal(b["sign"], -a["sign"])
+    np.testing.assert_allclose(b["logabs"], a["logabs"], rtol=1e-12, atol=1e-12)
+    gp = a["grad"].copy()
+    gp[:, [1, 4]] = gp[:, [4, 1]]
+    np.testing.assert_allclose(b["grad"], gp, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(b["eloc"], a["eloc"], rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 1e-3), (3, "fp32", 1e-3), (2, "bf16", 0.2), (3, "bf16", 0.2)])
+def test_mixed_precision_error_statement(pn, idx, prec, bound):
+    """Mixed modes: the network in FP32 (or BF16 operands with FP32
+    accumulation), determinants and E_loc in FP64.  The per-output error
+    against the FP64 oracle is printed; the bound only guards against
+    gross breakage."""
+    fx = load_fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    announce(f"{prec} error statement workload {idx}")
+    out, _ = _run(pn, w, fx["walkers"], pn._lib.PRECISIONS[prec])
+    rat = parity_ratios(out, fx)
+    summ = summarize(rat)
+    print(f"[{prec} cfg{idx}] p50/p99/max: {summ}")
+    np.testing.assert_array_equal(out["sign"], fx["sign"])
+    assert summ["eloc"][1] < bound and summ["logabs"][1] < bound
