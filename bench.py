@@ -54,12 +54,17 @@ def chunk_T(s, net, prec):
     """Same chunk choice as the library's planner (LDS budget per block)."""
     N, DX, DZ = s.n_elec, net.dim_x, net.dim_z
     tn = 8 if prec == "fp64" else 4
-    budget = (84 if prec == "fp64" else 66) * 1024
+    pad = 16 // tn
+    LDX, LDZ = DX + pad, DZ + pad
+    LDHZ = max(2 * LDZ, LDX)
     for nc in range(1, 3 * N + 1):
         T = -(-3 * N // nc)
+        if T > 15:
+            continue
         C = T + 1
-        lds = 3 * 64 * 8 + N * C * (DX + max(DX, DZ) + DZ) * tn + 3 * C * DX * tn
-        if lds <= budget or T == 1:
+        R = N * C
+        lds = 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + (N * DZ + R * (LDX + LDHZ) + 2 * C * LDX) * tn
+        if lds <= 80 * 1024 or T == 1:
             return T
     return 1
 

@@ -35,9 +35,10 @@
  *    cancelling determinant sum gives logabs = -inf and sign = 0.
  *  - Electrons 0..n_up-1 are spin up, the rest spin down.  Coordinates are
  *    in bohr, energies in hartree.
- *  - Limits: n_up, n_down <= 32; n_elec <= 64; n_det <= 64; dim_x <= 128;
- *    dim_z <= 128; n_feat <= 64; shells are s (l = 0) or p (l = 1).
- *    Anything else returns PN_ERR_UNSUPPORTED_SHAPE.
+ *  - Limits: n_up, n_down <= 32; n_elec <= 64; n_det <= 64; n_nuc <= 64;
+ *    n_feat, dim_x and dim_z each one of 16, 32, 64, 128; n_mo <= dim_x;
+ *    n_layers <= 8; shells are s (l = 0) or p (l = 1).  Anything else
+ *    returns PN_ERR_UNSUPPORTED_SHAPE.
  */
 #ifndef PAULINET_H
 #define PAULINET_H

@@ -12,6 +12,7 @@
 // Rows of a block are (walker, pair) of one channel; pairs of a channel are
 // contiguous in the unified pair list (same-spin ee, opposite-spin ee, e-n).
 #include "gemm_lds.h"
+#include "mfma_gemm.h"
 #include "pn_internal.h"
 
 namespace pn {
@@ -31,9 +32,11 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
   if (np == 0 || row0 >= nrows) return;
   const int rows = (int)min((int64_t)PT, nrows - row0);
   const int K = d.K, DZ = d.DZ;
-  TN* E = reinterpret_cast<TN*>(smem);         // [3][PT][K]
-  TN* U = E + 3 * PT * K;                      // [3][PT][DZ]
-  double* dd = reinterpret_cast<double*>(U + 3 * PT * DZ);  // [PT]
+  const int LDK = ld_pad<TN>(K), LDZ = ld_pad<TN>(DZ);
+  double* dd = reinterpret_cast<double*>(smem);   // [PT]
+  TN* E = reinterpret_cast<TN*>(dd + PT);         // [3][PT][LDK]
+  TN* U = E + 3 * PT * LDK;                       // [3][PT][LDZ]
+  TN* O = U + 3 * PT * LDZ;                       // [3][PT][LDZ]
 
   // --- distances ---
   for (int q = threadIdx.x; q < rows; q += blockDim.x) {
@@ -63,50 +66,55 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
     double dm = dv - t.feat_mu[k], s = t.feat_sig2inv[k];
     double eg = exp(-dv - dm * dm * s);
     double g1 = -1.0 - 2.0 * dm * s, g2 = -2.0 * s;
-    E[(0 * PT + row) * K + k] = (TN)(dv * dv * eg);
-    E[(1 * PT + row) * K + k] = (TN)((2.0 + dv * g1) * eg);                              // e'/d
-    E[(2 * PT + row) * K + k] = (TN)((2.0 + 4.0 * dv * g1 + dv * dv * (g1 * g1 + g2)) * eg);  // e''
+    E[(0 * PT + row) * LDK + k] = (TN)(dv * dv * eg);
+    E[(1 * PT + row) * LDK + k] = (TN)((2.0 + dv * g1) * eg);                                  // e'/d
+    E[(2 * PT + row) * LDK + k] = (TN)((2.0 + 4.0 * dv * g1 + dv * dv * (g1 * g1 + g2)) * eg);  // e''
   }
-  for (int q = rows + threadIdx.x; q < PT; q += blockDim.x) dd[q] = 1.0;
   __syncthreads();
   const ParamLayout::Layer& Lp = pl.layer[layer];
-  // --- first Linear on all three jet rows; rows beyond `rows` are garbage-free zeros ---
+  // --- first Linear on the three jets ---
   for (int jet = 0; jet < 3; ++jet)
-    gemm_xw<TN>(E + jet * PT * K, K, rows, K, P + Lp.w1W[ch], DZ, U + jet * PT * DZ, DZ, false, bf16);
+    gemm_mfma<TN>(E + jet * PT * LDK, LDK, rows, K, P + Lp.w1W[ch], DZ, U + jet * PT * LDZ, LDZ, false, bf16);
   __syncthreads();
   // --- ssp jets, in place; bias on the value ---
   for (int q = threadIdx.x; q < rows * DZ; q += blockDim.x) {
     int row = q / DZ, z = q % DZ;
-    TN u = U[row * DZ + z] + P[Lp.w1b[ch] + z];
-    TN ud = U[(PT + row) * DZ + z];
-    TN u2 = U[(2 * PT + row) * DZ + z];
+    TN* u0 = U + row * LDZ + z;
+    TN u = u0[0] + P[Lp.w1b[ch] + z];
+    TN ud = u0[PT * LDZ];
+    TN u2 = u0[2 * PT * LDZ];
     TN sg = sigmoid_d(u);
-    TN dv = (TN)dd[row];
-    TN up = dv * ud;
-    U[row * DZ + z] = ssp(u);
-    U[(PT + row) * DZ + z] = sg * ud;
-    U[(2 * PT + row) * DZ + z] = sg * u2 + sg * (TN(1) - sg) * up * up;
+    TN up = (TN)dd[row] * ud;
+    u0[0] = ssp(u);
+    u0[PT * LDZ] = sg * ud;
+    u0[2 * PT * LDZ] = sg * u2 + sg * (TN(1) - sg) * up * up;
   }
   __syncthreads();
-  // --- second Linear, written straight to global as [walker][layer][jet][pair][DZ] ---
+  // --- second Linear ---
+  for (int jet = 0; jet < 3; ++jet)
+    gemm_mfma<TN>(U + jet * PT * LDZ, LDZ, rows, DZ, P + Lp.w2W[ch], DZ, O + jet * PT * LDZ, LDZ, false, bf16);
+  __syncthreads();
+  // --- store as [walker][layer][jet][pair][DZ]; bias on the value ---
   const int64_t lstride = (int64_t)3 * d.n_pairs * DZ;
-  for (int jet = 0; jet < 3; ++jet) {
-    const TN* X = U + jet * PT * DZ;
-    const TN* W = P + Lp.w2W[ch];
-    for (int q = threadIdx.x; q < rows * DZ; q += blockDim.x) {
-      int row = q / DZ, o = q % DZ;
-      TN acc = jet == 0 ? P[Lp.w2b[ch] + o] : TN(0);
-      const TN* xr = X + row * DZ;
-      for (int k = 0; k < DZ; ++k) acc += maybe_bf16(xr[k], bf16) * maybe_bf16(W[k * DZ + o], bf16);
-      int64_t g = row0 + row;
-      int64_t w = g / np;
-      int p = p_lo + (int)(g % np);
-      filt[w * (int64_t)d.L * lstride + layer * lstride + ((int64_t)jet * d.n_pairs + p) * DZ + o] = acc;
-    }
+  for (int q = threadIdx.x; q < 3 * rows * DZ; q += blockDim.x) {
+    int jet = q / (rows * DZ), rem = q % (rows * DZ), row = rem / DZ, o = rem % DZ;
+    TN v = O[(jet * PT + row) * LDZ + o];
+    if (jet == 0) v += P[Lp.w2b[ch] + o];
+    int64_t g = row0 + row;
+    int64_t w = g / np;
+    int p = p_lo + (int)(g % np);
+    filt[w * (int64_t)d.L * lstride + layer * lstride + ((int64_t)jet * d.n_pairs + p) * DZ + o] = v;
   }
 }
 
 }  // namespace
+
+template <typename TN>
+size_t filter_lds_bytes(const Dims& d, int PT) {
+  return PT * sizeof(double) + (size_t)3 * PT * (ld_pad<TN>(d.K) + 2 * ld_pad<TN>(d.DZ)) * sizeof(TN);
+}
+template size_t filter_lds_bytes<double>(const Dims&, int);
+template size_t filter_lds_bytes<float>(const Dims&, int);
 
 template <typename TN>
 void launch_filters(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
@@ -118,7 +126,7 @@ void launch_filters(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r,
   n_same = d.n_up * (d.n_up - 1) / 2 + d.n_dn * (d.n_dn - 1) / 2;
   int64_t max_np = std::max<int64_t>(std::max(n_same, d.n_ee - n_same), (int64_t)d.N * d.NN);
   int64_t nbx = (nw * max_np + PT - 1) / PT;
-  size_t lds = (size_t)3 * PT * (d.K + d.DZ) * sizeof(TN) + PT * sizeof(double);
+  size_t lds = filter_lds_bytes<TN>(d, PT);
   hipLaunchKernelGGL(k_filters<TN>, dim3((unsigned)nbx, 3 * d.L), dim3(kThreads), lds, s, d, c->t, nw, r, P,
                      c->pl, reinterpret_cast<TN*>(ws + L.filt), PT, n_same, bf16);
 }

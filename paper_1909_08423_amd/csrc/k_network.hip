@@ -24,6 +24,7 @@
 // and d2_a w_ij = w'' u_a^2 + (w'/d)(1 - u_a^2), u = (r_i - r_j) / d_ij, for
 // k in {i, j}.
 #include "gemm_lds.h"
+#include "mfma_gemm.h"
 #include "pn_internal.h"
 
 namespace pn {
@@ -43,28 +44,30 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
   const int nwb = (int)min((int64_t)WPB, nw - w0);
   if (nwb <= 0) return;
   const int R = nwb * N;
-  const int DW = max(DX, DZ);
-  TN* X = reinterpret_cast<TN*>(smem);  // [WPB*N][DX]
-  TN* H = X + WPB * N * DX;              // [WPB*N][DW]
-  TN* Z = H + WPB * N * DW;              // [WPB*N][DW]
-  TN* E = Z + WPB * N * DW;              // [2][WPB][DX] Jastrow scratch
+  const int LDX = ld_pad<TN>(DX), LDW = ld_pad<TN>(max(DX, DZ));
+  int* pidx = reinterpret_cast<int*>(smem);                      // [N][N]
+  TN* X = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));      // [WPB*N][LDX]
+  TN* H = X + WPB * N * LDX;                                     // [WPB*N][LDW]
+  TN* Z = H + WPB * N * LDW;                                     // [WPB*N][LDW]
+  TN* E = Z + WPB * N * LDW;                                     // [2][WPB][LDX] Jastrow scratch
   const int64_t fl_stride = (int64_t)3 * d.n_pairs * DZ;  // per layer
   const int64_t fw_stride = fl_stride * d.L;               // per walker
 
-  for (int q = threadIdx.x; q < R * DX; q += blockDim.x) X[q] = P[pl.x0 + q % DX];
+  for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
+  for (int q = threadIdx.x; q < R * DX; q += blockDim.x) X[(q / DX) * LDX + q % DX] = P[pl.x0 + q % DX];
   __syncthreads();
   for (int n = 0; n < d.L; ++n) {
     const ParamLayout::Layer& Lp = pl.layer[n];
     if (xval)
       for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
-        xval[((w0 + q / (N * DX)) * (d.L + 1) + n) * N * DX + q % (N * DX)] = X[q];
-    gemm_xw<TN>(X, DX, R, DX, P + Lp.hW, DZ, H, DZ, false, bf16);
+        xval[((w0 + q / (N * DX)) * (d.L + 1) + n) * N * DX + q % (N * DX)] = X[(q / DX) * LDX + q % DX];
+    gemm_mfma<TN>(X, LDX, R, DX, P + Lp.hW, DZ, H, LDW, false, bf16);
     __syncthreads();
     for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
-      TN v = H[q] + P[Lp.hb + q % DZ];
-      H[q] = v;
-      int row = q / DZ;
-      hval[((w0 + row / N) * d.L + n) * N * DZ + (row % N) * DZ + q % DZ] = v;
+      const int row = q / DZ, z = q % DZ;
+      TN v = H[row * LDW + z] + P[Lp.hb + z];
+      H[row * LDW + z] = v;
+      hval[((w0 + row / N) * d.L + n) * N * DZ + (row % N) * DZ + z] = v;
     }
     __syncthreads();
     for (int ch = 0; ch < 3; ++ch) {
@@ -78,8 +81,8 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
             if (j == i) continue;
             bool same = (j < d.n_up) == up_i;
             if (same != (ch == 0)) continue;
-            int p = t.pair_index[i * N + j];
-            acc += fw[(int64_t)p * DZ + z] * H[(wl * N + j) * DZ + z];
+            int p = pidx[i * N + j];
+            acc += fw[(int64_t)p * DZ + z] * H[(wl * N + j) * LDW + z];
           }
         } else {
           for (int I = 0; I < d.NN; ++I) {
@@ -87,93 +90,81 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
             acc += fw[(int64_t)p * DZ + z] * P[pl.Y + I * DZ + z];
           }
         }
-        Z[q] = acc;
+        Z[row * LDW + z] = acc;
       }
       __syncthreads();
-      gemm_xw<TN>(Z, DZ, R, DZ, P + Lp.gW[ch], DX, X, DX, true, bf16);
+      gemm_mfma<TN>(Z, LDW, R, DZ, P + Lp.gW[ch], DX, X, LDX, true, bf16);
       __syncthreads();
-      for (int q = threadIdx.x; q < R * DX; q += blockDim.x) X[q] += P[Lp.gb[ch] + q % DX];
+      for (int q = threadIdx.x; q < R * DX; q += blockDim.x) X[(q / DX) * LDX + q % DX] += P[Lp.gb[ch] + q % DX];
       __syncthreads();
     }
   }
   if (xval)
     for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
-      xval[((w0 + q / (N * DX)) * (d.L + 1) + d.L) * N * DX + q % (N * DX)] = X[q];
+      xval[((w0 + q / (N * DX)) * (d.L + 1) + d.L) * N * DX + q % (N * DX)] = X[(q / DX) * LDX + q % DX];
   // ---- Jastrow head on s = sum_i x_i (rows = walkers) ----
-  TN* S = E;               // [WPB][DX]
-  TN* U = E + WPB * DX;    // [WPB][DX]
+  TN* S = E;                // [WPB][LDX]
+  TN* U = E + WPB * LDX;    // [WPB][LDX]
   for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
     int wl = q / DX, x = q % DX;
     TN s = 0;
-    for (int i = 0; i < N; ++i) s += X[(wl * N + i) * DX + x];
-    S[q] = s;
+    for (int i = 0; i < N; ++i) s += X[(wl * N + i) * LDX + x];
+    S[wl * LDX + x] = s;
   }
   __syncthreads();
   for (int lay = 0; lay < 2; ++lay) {
-    gemm_xw<TN>(S, DX, nwb, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, U, DX, false, bf16);
+    gemm_mfma<TN>(S, LDX, nwb, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, U, LDX, false, bf16);
     __syncthreads();
     for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
       int wl = q / DX, x = q % DX;
-      TN u = U[q] + P[(lay == 0 ? pl.eb1 : pl.eb2) + x];
+      TN u = U[wl * LDX + x] + P[(lay == 0 ? pl.eb1 : pl.eb2) + x];
       TN sg = sigmoid_d(u);
       ecoef[((w0 + wl) * 2 + lay) * 2 * DX + x] = sg;
       ecoef[((w0 + wl) * 2 + lay) * 2 * DX + DX + x] = sg * (TN(1) - sg);
-      S[q] = ssp(u);
+      S[wl * LDX + x] = ssp(u);
     }
     __syncthreads();
   }
   for (int wl = threadIdx.x; wl < nwb; wl += blockDim.x) {
     TN acc = P[pl.eb3];
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S[wl * DX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S[wl * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
     jval[w0 + wl] = (double)acc;
   }
   __syncthreads();
   // ---- backflow head, per electron row ----
-  TN* A1 = H;  // [R][DX]
-  gemm_xw<TN>(X, DX, R, DX, P + pl.kW1, DX, A1, DX, false, bf16);
+  gemm_mfma<TN>(X, LDX, R, DX, P + pl.kW1, DX, H, LDW, false, bf16);
   __syncthreads();
   for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
     int row = q / DX, x = q % DX;
-    TN u = A1[q] + P[pl.kb1 + x];
+    TN u = H[row * LDW + x] + P[pl.kb1 + x];
     TN sg = sigmoid_d(u);
     kcoef[(((w0 + row / N) * 2 + 0) * 2 + 0) * N * DX + (row % N) * DX + x] = sg;
     kcoef[(((w0 + row / N) * 2 + 0) * 2 + 1) * N * DX + (row % N) * DX + x] = sg * (TN(1) - sg);
-    A1[q] = ssp(u);
+    H[row * LDW + x] = ssp(u);
   }
   __syncthreads();
-  gemm_xw<TN>(A1, DX, R, DX, P + pl.kW2, DX, X, DX, false, bf16);
+  gemm_mfma<TN>(H, LDW, R, DX, P + pl.kW2, DX, X, LDX, false, bf16);
   __syncthreads();
   for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
     int row = q / DX, x = q % DX;
-    TN u = X[q] + P[pl.kb2 + x];
+    TN u = X[row * LDX + x] + P[pl.kb2 + x];
     TN sg = sigmoid_d(u);
     kcoef[(((w0 + row / N) * 2 + 1) * 2 + 0) * N * DX + (row % N) * DX + x] = sg;
     kcoef[(((w0 + row / N) * 2 + 1) * 2 + 1) * N * DX + (row % N) * DX + x] = sg * (TN(1) - sg);
-    X[q] = ssp(u);
+    X[row * LDX + x] = ssp(u);
   }
   __syncthreads();
   for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
     int row = q / M, mu = q % M;
     TN acc = P[pl.kb3 + mu];
-    const TN* xr = X + row * DX;
+    const TN* xr = X + row * LDX;
     for (int x = 0; x < DX; ++x) acc += maybe_bf16(xr[x], bf16) * maybe_bf16(P[pl.kW3 + x * M + mu], bf16);
     fval[(w0 + row / N) * N * M + (row % N) * M + mu] = 1.0 + (double)acc;
   }
 }
 
 // -------------------------------------------------------------- tangents --
-struct ChunkInfo {
-  int a0, T, C;  // first coordinate, coordinates in the chunk, columns = T + 1
-};
-
-template <typename TN>
-__device__ __forceinline__ void pair_geom(const double* rs, int i, int j, double& d, double* u) {
-  double x = rs[3 * i] - rs[3 * j], y = rs[3 * i + 1] - rs[3 * j + 1], z = rs[3 * i + 2] - rs[3 * j + 2];
-  d = sqrt(x * x + y * y + z * z);
-  u[0] = x;
-  u[1] = y;
-  u[2] = z;
-}
+constexpr int kCMax = 16;  // columns per chunk (T + 1) held in registers
 
 template <typename TN>
 __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
@@ -201,166 +192,188 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
   const int C = Tc + 1;   // tangent columns + partial-Laplacian column
   const int LC = Tc;      // index of the Laplacian column
   const int R = N * C;    // rows: (electron i, column)
-  const int DW = max(DX, DZ);
-  double* rs = reinterpret_cast<double*>(smem);  // [N][3]
-  TN* XT = reinterpret_cast<TN*>(rs + 3 * kMaxElec);  // [R][DX]
-  TN* HT = XT + R * DX;                                 // [R][DW]
-  TN* ZT = HT + R * DW;                                 // [R][DZ]
-  TN* ES = ZT + R * DZ;                                 // [3][C][DX] Jastrow scratch
+  const int e_lo = a0 / 3, e_hi = (a0 + Tc - 1) / 3;  // electrons with coordinates in the chunk
+  const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDHZ = max(2 * LDZ, LDX);
+  double* rs = reinterpret_cast<double*>(smem);             // [N][3]
+  int* pidx = reinterpret_cast<int*>(rs + 3 * kMaxElec);    // [N][N]
+  TN* hvs = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));  // [N][DZ]
+  TN* XT = hvs + N * DZ;                                    // [R][LDX]
+  TN* HT = XT + R * LDX;                                    // [R][LDZ]  (layers)
+  TN* ZT = HT + R * LDZ;                                    // [R][LDZ]  (layers)
+  TN* KT = HT;                                              // [R][LDX]  (backflow head, over HT and ZT)
+  TN* ES = HT + R * LDHZ;                                   // [2][C][LDX] Jastrow scratch
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
-  for (int q = threadIdx.x; q < R * DX; q += blockDim.x) XT[q] = 0;
+  for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
+  for (int q = threadIdx.x; q < R * LDX; q += blockDim.x) XT[q] = 0;
   __syncthreads();
   const int64_t fl_stride = (int64_t)3 * d.n_pairs * DZ;
   for (int n = 0; n < d.L; ++n) {
     const ParamLayout::Layer& Lp = pl.layer[n];
     const TN* fw = filt + w * fl_stride * d.L + n * fl_stride;
-    const TN* fv = fw;                              // w
-    const TN* fd = fw + (int64_t)d.n_pairs * DZ;    // w'/d
-    const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;  // w''
+    const TN* fv = fw;                                 // w
+    const TN* fd = fw + (int64_t)d.n_pairs * DZ;       // w'/d
+    const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
     const TN* hv = hval + (w * d.L + n) * N * DZ;
-    if (n > 0) {
-      gemm_xw<TN>(XT, DX, R, DX, P + Lp.hW, DZ, HT, DZ, false, bf16);
-    } else {
-      for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) HT[q] = 0;
-    }
+    for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) hvs[q] = hv[q];
+    if (n > 0) gemm_mfma<TN>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
     __syncthreads();
-    for (int ch = 0; ch < 3; ++ch) {
-      for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
-        const int row = q / DZ, z = q % DZ, i = row / C, col = row % C;
-        TN acc = 0;
-        if (ch < 2) {
-          const bool up_i = i < d.n_up;
+    for (int ch = 0; ch < 2; ++ch) {
+      for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) {
+        const int i = q / DZ, z = q % DZ;
+        const bool up_i = i < d.n_up;
+        TN acc[kCMax];
+#pragma unroll
+        for (int c = 0; c < kCMax; ++c) acc[c] = 0;
+        if (n > 0) {
           for (int j = 0; j < N; ++j) {
             if (j == i || (((j < d.n_up) == up_i) != (ch == 0))) continue;
-            const int p = t.pair_index[i * N + j];
-            acc += fv[(int64_t)p * DZ + z] * HT[(j * C + col) * DZ + z];
-          }
-          if (col < LC) {
-            const int a = a0 + col, k = a / 3, al = a % 3;
-            if (k == i) {
-              for (int j = 0; j < N; ++j) {
-                if (j == i || (((j < d.n_up) == up_i) != (ch == 0))) continue;
-                const int p = t.pair_index[i * N + j];
-                TN dx = (TN)(rs[3 * i + al] - rs[3 * j + al]);
-                acc += fd[(int64_t)p * DZ + z] * dx * hv[j * DZ + z];
-              }
-            } else if (k != i && (((k < d.n_up) == up_i) == (ch == 0))) {
-              const int p = t.pair_index[i * N + k];
-              TN dx = (TN)(rs[3 * k + al] - rs[3 * i + al]);
-              acc += fd[(int64_t)p * DZ + z] * dx * hv[k * DZ + z];
-            }
-          } else {
-            // second-derivative and cross terms of the chunk's coordinates
-            for (int c2 = 0; c2 < LC; ++c2) {
-              const int a = a0 + c2, k = a / 3, al = a % 3;
-              if (k == i) {
-                for (int j = 0; j < N; ++j) {
-                  if (j == i || (((j < d.n_up) == up_i) != (ch == 0))) continue;
-                  const int p = t.pair_index[i * N + j];
-                  double dd, u[3];
-                  pair_geom<TN>(rs, i, j, dd, u);
-                  double ua = u[al] / dd;
-                  TN wd = fd[(int64_t)p * DZ + z], w2 = f2[(int64_t)p * DZ + z];
-                  TN d2w = w2 * (TN)(ua * ua) + wd * (TN)(1.0 - ua * ua);
-                  TN dw = wd * (TN)u[al];
-                  acc += d2w * hv[j * DZ + z] + TN(2) * dw * HT[(j * C + c2) * DZ + z];
-                }
-              } else if (((k < d.n_up) == up_i) == (ch == 0)) {
-                const int p = t.pair_index[i * N + k];
-                double dd, u[3];
-                pair_geom<TN>(rs, i, k, dd, u);
-                double ua = u[al] / dd;
-                TN wd = fd[(int64_t)p * DZ + z], w2 = f2[(int64_t)p * DZ + z];
-                TN d2w = w2 * (TN)(ua * ua) + wd * (TN)(1.0 - ua * ua);
-                TN dw = -wd * (TN)u[al];  // d/dr_k of d_ik
-                acc += d2w * hv[k * DZ + z] + TN(2) * dw * HT[(k * C + c2) * DZ + z];
-              }
-            }
-          }
-        } else {
-          // nuclear channel: only coordinates of electron i itself contribute
-          for (int I = 0; I < d.NN; ++I) {
-            const int p = d.n_ee + i * d.NN + I;
-            double u[3] = {rs[3 * i] - t.nuc_xyz[3 * I], rs[3 * i + 1] - t.nuc_xyz[3 * I + 1],
-                           rs[3 * i + 2] - t.nuc_xyz[3 * I + 2]};
-            double dd = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            TN y = P[pl.Y + I * DZ + z];
-            TN wd = fd[(int64_t)p * DZ + z];
-            if (col < LC) {
-              const int a = a0 + col, k = a / 3, al = a % 3;
-              if (k == i) acc += wd * (TN)u[al] * y;
-            } else {
-              TN w2 = f2[(int64_t)p * DZ + z];
-              for (int c2 = 0; c2 < LC; ++c2) {
-                const int a = a0 + c2, k = a / 3, al = a % 3;
-                if (k != i) continue;
-                double ua = u[al] / dd;
-                acc += (w2 * (TN)(ua * ua) + wd * (TN)(1.0 - ua * ua)) * y;
-              }
-            }
+            const TN wv = fv[(int64_t)pidx[i * N + j] * DZ + z];
+            const TN* hj = HT + (size_t)j * C * LDZ + z;
+#pragma unroll
+            for (int c = 0; c < kCMax; ++c)
+              if (c < C) acc[c] += wv * hj[c * LDZ];
           }
         }
-        ZT[q] = acc;
+        TN* zi = ZT + (size_t)i * C * LDZ + z;
+#pragma unroll
+        for (int c = 0; c < kCMax; ++c)
+          if (c < C) zi[c * LDZ] = acc[c];
+        // derivatives of the filters with respect to the chunk's coordinates
+        TN lap = 0;
+        if (i >= e_lo && i <= e_hi) {
+          for (int al = 0; al < 3; ++al) {
+            const int c = 3 * i + al - a0;
+            if (c < 0 || c >= Tc) continue;
+            TN sv = 0;
+            for (int j = 0; j < N; ++j) {
+              if (j == i || (((j < d.n_up) == up_i) != (ch == 0))) continue;
+              const int64_t p = pidx[i * N + j];
+              const double ux = rs[3 * i] - rs[3 * j], uy = rs[3 * i + 1] - rs[3 * j + 1],
+                           uz = rs[3 * i + 2] - rs[3 * j + 2];
+              const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+              const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
+              const double ur = ua / dd;
+              const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+              const TN dw = wd * (TN)ua;
+              sv += dw * hvs[j * DZ + z];
+              lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * hvs[j * DZ + z];
+              if (n > 0) lap += TN(2) * dw * HT[((size_t)j * C + c) * LDZ + z];
+            }
+            zi[c * LDZ] += sv;
+          }
+        }
+        for (int k = e_lo; k <= e_hi; ++k) {
+          if (k == i || (((k < d.n_up) == up_i) != (ch == 0))) continue;
+          const int64_t p = pidx[i * N + k];
+          const double ux = rs[3 * i] - rs[3 * k], uy = rs[3 * i + 1] - rs[3 * k + 1], uz = rs[3 * i + 2] - rs[3 * k + 2];
+          const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+          const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+          for (int al = 0; al < 3; ++al) {
+            const int c = 3 * k + al - a0;
+            if (c < 0 || c >= Tc) continue;
+            const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
+            const double ur = ua / dd;
+            const TN dw = -wd * (TN)ua;  // d/dr_k of w(|r_i - r_k|)
+            zi[c * LDZ] += dw * hvs[k * DZ + z];
+            lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * hvs[k * DZ + z];
+            if (n > 0) lap += TN(2) * dw * HT[((size_t)k * C + c) * LDZ + z];
+          }
+        }
+        zi[LC * LDZ] += lap;
       }
       __syncthreads();
-      gemm_xw<TN>(ZT, DZ, R, DZ, P + Lp.gW[ch], DX, XT, DX, true, bf16);
+      gemm_mfma<TN>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
       __syncthreads();
     }
+    // nuclear channel: only the chunk's own electrons have non-zero rows
+    for (int q = threadIdx.x; q < (e_hi - e_lo + 1) * DZ; q += blockDim.x) {
+      const int i = e_lo + q / DZ, z = q % DZ;
+      TN* zi = ZT + (size_t)i * C * LDZ + z;
+      for (int c = 0; c < C; ++c) zi[c * LDZ] = 0;
+      TN lap = 0;
+      for (int I = 0; I < d.NN; ++I) {
+        const int64_t p = d.n_ee + i * d.NN + I;
+        const double ux = rs[3 * i] - t.nuc_xyz[3 * I], uy = rs[3 * i + 1] - t.nuc_xyz[3 * I + 1],
+                     uz = rs[3 * i + 2] - t.nuc_xyz[3 * I + 2];
+        const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+        const TN y = P[pl.Y + I * DZ + z];
+        const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+        for (int al = 0; al < 3; ++al) {
+          const int c = 3 * i + al - a0;
+          if (c < 0 || c >= Tc) continue;
+          const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
+          const double ur = ua / dd;
+          zi[c * LDZ] += wd * (TN)ua * y;
+          lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * y;
+        }
+      }
+      zi[LC * LDZ] = lap;
+    }
+    __syncthreads();
+    {
+      const int row0 = e_lo * C, nrow = (e_hi - e_lo + 1) * C;
+      gemm_mfma<TN>(ZT + (size_t)row0 * LDZ, LDZ, nrow, DZ, P + Lp.gW[2], DX, XT + (size_t)row0 * LDX, LDX, true,
+                    bf16);
+    }
+    __syncthreads();
   }
   // ---- Jastrow head on sum_i x_i, rows = columns ----
-  TN* S = ES;              // [C][DX]
-  TN* U = ES + C * DX;     // [C][DX]
+  TN* S0 = ES;             // [C][LDX]
+  TN* S1 = ES + C * LDX;   // [C][LDX]
   for (int q = threadIdx.x; q < C * DX; q += blockDim.x) {
     int col = q / DX, x = q % DX;
     TN s = 0;
-    for (int i = 0; i < N; ++i) s += XT[(i * C + col) * DX + x];
-    S[q] = s;
+    for (int i = 0; i < N; ++i) s += XT[((size_t)i * C + col) * LDX + x];
+    S0[col * LDX + x] = s;
   }
   __syncthreads();
   for (int lay = 0; lay < 2; ++lay) {
-    gemm_xw<TN>(S, DX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, U, DX, false, bf16);
+    TN* Sin = lay == 0 ? S0 : S1;
+    TN* Sout = lay == 0 ? S1 : S0;
+    gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
     __syncthreads();
     const TN* ec = ecoef + (w * 2 + lay) * 2 * DX;
     for (int x = threadIdx.x; x < DX; x += blockDim.x) {
       TN s1 = ec[x], s2 = ec[DX + x];
       TN sq = 0;
       for (int col = 0; col < LC; ++col) {
-        TN v = U[col * DX + x];
+        TN v = Sout[col * LDX + x];
         sq += v * v;
-        S[col * DX + x] = s1 * v;
+        Sout[col * LDX + x] = s1 * v;
       }
-      S[LC * DX + x] = s1 * U[LC * DX + x] + s2 * sq;
+      Sout[LC * LDX + x] = s1 * Sout[LC * LDX + x] + s2 * sq;
     }
     __syncthreads();
   }
   double* jt = jtan + ((int64_t)w * n_chunks + chunk) * (T + 1);
   for (int col = threadIdx.x; col < C; col += blockDim.x) {
     TN acc = 0;
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S[col * DX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
     jt[col == LC ? T : col] = (double)acc;
   }
-  __syncthreads();
   // ---- backflow head ----
-  gemm_xw<TN>(XT, DX, R, DX, P + pl.kW1, DX, HT, DX, false, bf16);
+  gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
   __syncthreads();
   for (int lay = 0; lay < 2; ++lay) {
-    TN* A = lay == 0 ? HT : XT;
+    TN* A = lay == 0 ? KT : XT;
+    const int LDA = LDX;
     const TN* kc = kcoef + (w * 2 + lay) * 2 * N * DX;
     for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
       int i = q / DX, x = q % DX;
       TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
       TN sq = 0;
+      TN* ai = A + (size_t)i * C * LDA + x;
       for (int col = 0; col < LC; ++col) {
-        TN v = A[(i * C + col) * DX + x];
+        TN v = ai[col * LDA];
         sq += v * v;
-        A[(i * C + col) * DX + x] = s1 * v;
+        ai[col * LDA] = s1 * v;
       }
-      A[(i * C + LC) * DX + x] = s1 * A[(i * C + LC) * DX + x] + s2 * sq;
+      ai[LC * LDA] = s1 * ai[LC * LDA] + s2 * sq;
     }
     __syncthreads();
     if (lay == 0) {
-      gemm_xw<TN>(HT, DX, R, DX, P + pl.kW2, DX, XT, DX, false, bf16);
+      gemm_mfma<TN>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
       __syncthreads();
     }
   }
@@ -368,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
   for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
     int row = q / M, mu = q % M, i = row / C, col = row % C;
     TN acc = 0;
-    const TN* xr = XT + row * DX;
+    const TN* xr = XT + (size_t)row * LDX;
     for (int x = 0; x < DX; ++x) acc += maybe_bf16(xr[x], bf16) * maybe_bf16(P[pl.kW3 + x * M + mu], bf16);
     ft[((int64_t)i * (T + 1) + (col == LC ? T : col)) * M + mu] = (double)acc;
   }
@@ -408,13 +421,16 @@ void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double
 
 template <typename TN>
 size_t tangent_lds_bytes(const Dims& d, int T) {
-  int C = T + 1, R = d.N * C, DW = std::max(d.DX, d.DZ);
-  return 3 * kMaxElec * sizeof(double) + (size_t)R * (d.DX + DW + d.DZ) * sizeof(TN) + 3 * C * d.DX * sizeof(TN);
+  const int C = T + 1, R = d.N * C;
+  const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
+  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
+         ((size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX) * sizeof(TN);
 }
 template <typename TN>
 size_t value_lds_bytes(const Dims& d, int wpb) {
-  int DW = std::max(d.DX, d.DZ);
-  return ((size_t)wpb * d.N * (d.DX + 2 * DW) + 2 * (size_t)wpb * d.DX) * sizeof(TN);
+  const int LDX = ld_pad<TN>(d.DX), LDW = ld_pad<TN>(std::max(d.DX, d.DZ));
+  return (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
+         ((size_t)wpb * d.N * (LDX + 2 * LDW) + 2 * (size_t)wpb * LDX) * sizeof(TN);
 }
 
 template void launch_net_value<double>(const pn_ctx*, hipStream_t, int64_t, const double*, char*, const WsLayout&,

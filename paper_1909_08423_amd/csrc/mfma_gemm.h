@@ -1,0 +1,165 @@
+// Dense products on the CDNA4 matrix cores, for the fused network kernels:
+//
+//   Y[rows][O] (+)= X[rows][I] * W[I][O]
+//
+// X and Y live in LDS (row strides ldx, ldy), W is a parameter block in
+// global memory ([I][O] row-major, shared by every workgroup, read through
+// L1/L2).  The output is cut into 16 x 16 tiles; each wavefront of the
+// block keeps one 16-column slab of W in registers and walks row tiles.
+//
+// Instructions (wave64):
+//   FP64           v_mfma_f64_16x16x4_f64     (one k per lane and step)
+//   FP32           v_mfma_f32_16x16x4_f32
+//   BF16 operands  v_mfma_f32_16x16x32_bf16   (I % 32 == 0) or
+//                  v_mfma_f32_16x16x16_bf16   (I % 16 == 0), FP32 accumulate
+//
+// The reduction index is split so that lane group g = lane / 16 covers a
+// contiguous range of I / 4 values of k: each lane then reads its A operand
+// as contiguous LDS words, and every step still sums over distinct k.
+//
+// Output layout of the 16 x 16 result (checked on gfx950): lane l, element
+// v holds row 4 (l / 16) + v (FP32 and BF16 forms) or row 4 v + l / 16
+// (FP64 form), column l % 16.
+//
+// Requirements: O % 16 == 0; I in {16, 32, 64, 128}; rows >= 1.  Rows past `rows` read a clamped row and are not stored.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  // round to nearest even
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+template <typename TN>
+struct MfmaTile;
+
+template <>
+struct MfmaTile<double> {
+  typedef v4d acc_t;
+  __device__ static int row_of(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct MfmaTile<float> {
+  typedef v4f acc_t;
+  __device__ static int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// One wavefront: C += A_tile(16 x I) * B_slab(I x 16), operands in registers
+// (afrag[s] = X[row][g*KQ + s], bfrag[s] = W[g*KQ + s][col]).
+template <typename TN, int KQ>
+struct MfmaChain;
+
+template <int KQ>
+struct MfmaChain<double, KQ> {
+  __device__ static v4d run(const double* a, const double* b, v4d c, bool) {
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
+};
+
+template <int KQ>
+struct MfmaChain<float, KQ> {
+  __device__ static v4f run(const float* a, const float* b, v4f c, bool bf16) {
+    if (!bf16) {
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+      return c;
+    }
+    if constexpr ((KQ % 8) == 0) {
+#pragma unroll
+      for (int s = 0; s < KQ; s += 8) {
+        v8bf av, bv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          av[q] = __builtin_bit_cast(__bf16, bf16_bits(a[s + q]));
+          bv[q] = __builtin_bit_cast(__bf16, bf16_bits(b[s + q]));
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KQ; s += 4) {
+        v4s av, bv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          av[q] = bf16_bits(a[s + q]);
+          bv[q] = bf16_bits(b[s + q]);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+      }
+    }
+    return c;
+  }
+};
+
+template <typename TN, int KQ>
+__device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int O, TN* Y,
+                                            int ldy, bool accumulate, bool bf16) {
+  typedef typename MfmaTile<TN>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int n_rt = (rows + 15) >> 4, n_ct = O >> 4;
+  int ct0, ct_step, rt0, rt_step;
+  if (n_ct >= nwv || (nwv % n_ct) != 0) {
+    ct0 = wv;
+    ct_step = nwv;
+    rt0 = 0;
+    rt_step = 1;
+  } else {
+    ct0 = wv % n_ct;
+    ct_step = O;  // a single slab per wave
+    rt0 = wv / n_ct;
+    rt_step = nwv / n_ct;
+  }
+  for (int ct = ct0; ct < n_ct; ct += ct_step) {
+    const int col = (ct << 4) + c16;
+    TN bfrag[KQ];
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) bfrag[s] = W[(size_t)(g * KQ + s) * O + col];
+    for (int rt = rt0; rt < n_rt; rt += rt_step) {
+      const int r = min((rt << 4) + c16, rows - 1);
+      const TN* xr = X + (size_t)r * ldx + g * KQ;
+      TN afrag[KQ];
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) afrag[s] = xr[s];
+      acc_t c;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
+        c[v] = (accumulate && row < rows) ? Y[(size_t)row * ldy + col] : TN(0);
+      }
+      c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
+        if (row < rows) Y[(size_t)row * ldy + col] = c[v];
+      }
+    }
+  }
+}
+
+// Whole-block product; every thread of the block must call it.  I must be
+// one of 16, 32, 64, 128; O a multiple of 16.
+template <typename TN>
+__device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W, int O,
+                                          TN* Y, int ldy, bool accumulate, bool bf16) {
+  switch (I) {
+    case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
+    case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
+    case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
+    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
+  }
+}
+
+}  // namespace pn

@@ -16,6 +16,9 @@ size_t tangent_lds_bytes(const Dims& d, int T);
 template <typename TN>
 size_t value_lds_bytes(const Dims& d, int wpb);
 size_t slater_tangent_lds_bytes(const Dims& d, int T);
+template <typename TN>
+size_t filter_lds_bytes(const Dims& d, int PT);
+constexpr int kMaxChunk = 15;  // coordinates per tangent chunk (columns T + 1 <= 16)
 void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
                      bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params);
 size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32);
@@ -121,11 +124,12 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   const size_t tn = fp64 ? sizeof(double) : sizeof(float);
   WsLayout L{};
   // chunking of the 3N coordinates for the tangent pass
-  const size_t budget = fp64 ? 84 * 1024 : 66 * 1024;
+  const size_t budget = 80 * 1024;
   const int ncoord = 3 * d.N;
   L.T = 1;
   for (int nc = 1; nc <= ncoord; ++nc) {
     int T = (ncoord + nc - 1) / nc;
+    if (T > kMaxChunk) continue;
     size_t lds = fp64 ? tangent_lds_bytes<double>(d, T) : tangent_lds_bytes<float>(d, T);
     if (lds <= budget || T == 1) {
       L.T = T;
@@ -140,9 +144,10 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
     L.wpb_value /= 2;
   L.lds_value = fp64 ? value_lds_bytes<double>(d, L.wpb_value) : value_lds_bytes<float>(d, L.wpb_value);
   L.filt_rows = 64;
-  while (L.filt_rows > 8 && (size_t)3 * L.filt_rows * (d.K + d.DZ) * tn + L.filt_rows * 8 > 64 * 1024)
+  while (L.filt_rows > 16 &&
+         (fp64 ? filter_lds_bytes<double>(d, L.filt_rows) : filter_lds_bytes<float>(d, L.filt_rows)) > 64 * 1024)
     L.filt_rows /= 2;
-  L.lds_filter = (size_t)3 * L.filt_rows * (d.K + d.DZ) * tn + L.filt_rows * 8;
+  L.lds_filter = fp64 ? filter_lds_bytes<double>(d, L.filt_rows) : filter_lds_bytes<float>(d, L.filt_rows);
 
   const int N = d.N, M = d.M, P = d.P, Tp = L.T + 1;
   const size_t gsz = (size_t)d.n_up * d.n_up + (size_t)d.n_dn * d.n_dn;
@@ -265,6 +270,8 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   if (net->n_feat < 1 || net->dim_x < 1 || net->dim_z < 1 || net->n_layers < 1 || !(net->feat_cutoff > 0))
     return PN_ERR_INVALID_ARG;
   const int N = sys->n_up + sys->n_down;
+  auto mfma_dim = [](int v) { return v == 16 || v == 32 || v == 64 || v == 128; };
+  if (!mfma_dim(net->n_feat) || !mfma_dim(net->dim_x) || !mfma_dim(net->dim_z)) return PN_ERR_UNSUPPORTED_SHAPE;
   if (sys->n_up > kMaxSpin || sys->n_down > kMaxSpin || N > kMaxElec || sys->n_det > kMaxDet ||
       net->dim_x > 128 || net->dim_z > 128 || net->n_feat > 64 || net->n_layers > kMaxLayers ||
       sys->n_nuc > kMaxNuc || sys->n_mo > net->dim_x)

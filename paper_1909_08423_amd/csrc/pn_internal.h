@@ -140,9 +140,11 @@ __device__ __forceinline__ float ssp(float x) {
   return (x > 0.f ? x + log1pf(__expf(-x)) : log1pf(__expf(x))) - 0.69314718f;
 }
 
+// LDS row stride with 16 bytes of padding (keeps 16-byte alignment, spreads
+// rows over the banks).
 template <typename T>
-__device__ __forceinline__ T load_param(const T* p, int64_t i) {
-  return p[i];
+__host__ __device__ constexpr int ld_pad(int D) {
+  return D + 16 / (int)sizeof(T);
 }
 
 }  // namespace pn
