@@ -63,7 +63,9 @@ def chunk_T(s, net, prec):
             continue
         C = T + 1
         R = N * C
-        lds = 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + (N * DZ + R * (LDX + LDHZ) + 2 * C * LDX) * tn
+        NCE = min(N, T // 3 + 2)
+        lds = (3 * 64 * 8 + ((N * N + 3) & ~3) * 4
+               + (N * DZ + R * (LDX + LDHZ) + 2 * C * LDX + NCE * (N + s.n_nuc) * 4) * tn)
         if lds <= 80 * 1024 or T == 1:
             return T
     return 1

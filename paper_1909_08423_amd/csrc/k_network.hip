@@ -154,12 +154,11 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
     X[row * LDX + x] = ssp(u);
   }
   __syncthreads();
+  gemm_mfma_cols<TN>(X, LDX, R, DX, P + pl.kW3, M, H, LDW, false, bf16);
+  __syncthreads();
   for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
     int row = q / M, mu = q % M;
-    TN acc = P[pl.kb3 + mu];
-    const TN* xr = X + row * LDX;
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(xr[x], bf16) * maybe_bf16(P[pl.kW3 + x * M + mu], bf16);
-    fval[(w0 + row / N) * N * M + (row % N) * M + mu] = 1.0 + (double)acc;
+    fval[(w0 + row / N) * N * M + (row % N) * M + mu] = 1.0 + (double)(H[row * LDW + mu] + P[pl.kb3 + mu]);
   }
 }
 
@@ -202,10 +201,32 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
   TN* ZT = HT + R * LDZ;                                    // [R][LDZ]  (layers)
   TN* KT = HT;                                              // [R][LDX]  (backflow head, over HT and ZT)
   TN* ES = HT + R * LDHZ;                                   // [2][C][LDX] Jastrow scratch
+  const int NCE = e_hi - e_lo + 1;
+  TN* cg = ES + 2 * C * LDX;                                // [NCE][N][4]  r_i - r_k, 1/|r_i - r_k|
+  TN* cgn = cg + NCE * N * 4;                               // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
   for (int q = threadIdx.x; q < R * LDX; q += blockDim.x) XT[q] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
+    const int k = e_lo + q / N, i = q % N;
+    const double ux = rs[3 * i] - rs[3 * k], uy = rs[3 * i + 1] - rs[3 * k + 1], uz = rs[3 * i + 2] - rs[3 * k + 2];
+    const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+    cg[4 * q + 0] = (TN)ux;
+    cg[4 * q + 1] = (TN)uy;
+    cg[4 * q + 2] = (TN)uz;
+    cg[4 * q + 3] = i == k ? TN(0) : (TN)(1.0 / dd);
+  }
+  for (int q = threadIdx.x; q < NCE * d.NN; q += blockDim.x) {
+    const int k = e_lo + q / d.NN, I = q % d.NN;
+    const double ux = rs[3 * k] - t.nuc_xyz[3 * I], uy = rs[3 * k + 1] - t.nuc_xyz[3 * I + 1],
+                 uz = rs[3 * k + 2] - t.nuc_xyz[3 * I + 2];
+    cgn[4 * q + 0] = (TN)ux;
+    cgn[4 * q + 1] = (TN)uy;
+    cgn[4 * q + 2] = (TN)uz;
+    cgn[4 * q + 3] = (TN)(1.0 / sqrt(ux * ux + uy * uy + uz * uz));
+  }
   __syncthreads();
   const int64_t fl_stride = (int64_t)3 * d.n_pairs * DZ;
   for (int n = 0; n < d.L; ++n) {
@@ -242,6 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
         // derivatives of the filters with respect to the chunk's coordinates
         TN lap = 0;
         if (i >= e_lo && i <= e_hi) {
+          const TN* gi = cg + (size_t)(i - e_lo) * N * 4;  // r_j - r_i
           for (int al = 0; al < 3; ++al) {
             const int c = 3 * i + al - a0;
             if (c < 0 || c >= Tc) continue;
@@ -249,15 +271,13 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
             for (int j = 0; j < N; ++j) {
               if (j == i || (((j < d.n_up) == up_i) != (ch == 0))) continue;
               const int64_t p = pidx[i * N + j];
-              const double ux = rs[3 * i] - rs[3 * j], uy = rs[3 * i + 1] - rs[3 * j + 1],
-                           uz = rs[3 * i + 2] - rs[3 * j + 2];
-              const double dd = sqrt(ux * ux + uy * uy + uz * uz);
-              const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
-              const double ur = ua / dd;
+              const TN ua = -gi[4 * j + al];  // (r_i - r_j)_alpha
+              const TN ur = ua * gi[4 * j + 3];
               const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
-              const TN dw = wd * (TN)ua;
-              sv += dw * hvs[j * DZ + z];
-              lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * hvs[j * DZ + z];
+              const TN dw = wd * ua;
+              const TN hj = hvs[j * DZ + z];
+              sv += dw * hj;
+              lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hj;
               if (n > 0) lap += TN(2) * dw * HT[((size_t)j * C + c) * LDZ + z];
             }
             zi[c * LDZ] += sv;
@@ -266,17 +286,17 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
         for (int k = e_lo; k <= e_hi; ++k) {
           if (k == i || (((k < d.n_up) == up_i) != (ch == 0))) continue;
           const int64_t p = pidx[i * N + k];
-          const double ux = rs[3 * i] - rs[3 * k], uy = rs[3 * i + 1] - rs[3 * k + 1], uz = rs[3 * i + 2] - rs[3 * k + 2];
-          const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+          const TN* gk = cg + ((size_t)(k - e_lo) * N + i) * 4;  // r_i - r_k
           const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+          const TN hk = hvs[k * DZ + z];
           for (int al = 0; al < 3; ++al) {
             const int c = 3 * k + al - a0;
             if (c < 0 || c >= Tc) continue;
-            const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
-            const double ur = ua / dd;
-            const TN dw = -wd * (TN)ua;  // d/dr_k of w(|r_i - r_k|)
-            zi[c * LDZ] += dw * hvs[k * DZ + z];
-            lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * hvs[k * DZ + z];
+            const TN ua = gk[al];
+            const TN ur = ua * gk[3];
+            const TN dw = -wd * ua;  // d/dr_k of w(|r_i - r_k|)
+            zi[c * LDZ] += dw * hk;
+            lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hk;
             if (n > 0) lap += TN(2) * dw * HT[((size_t)k * C + c) * LDZ + z];
           }
         }
@@ -294,18 +314,16 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
       TN lap = 0;
       for (int I = 0; I < d.NN; ++I) {
         const int64_t p = d.n_ee + i * d.NN + I;
-        const double ux = rs[3 * i] - t.nuc_xyz[3 * I], uy = rs[3 * i + 1] - t.nuc_xyz[3 * I + 1],
-                     uz = rs[3 * i + 2] - t.nuc_xyz[3 * I + 2];
-        const double dd = sqrt(ux * ux + uy * uy + uz * uz);
+        const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
         const TN y = P[pl.Y + I * DZ + z];
         const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
         for (int al = 0; al < 3; ++al) {
           const int c = 3 * i + al - a0;
           if (c < 0 || c >= Tc) continue;
-          const double ua = al == 0 ? ux : (al == 1 ? uy : uz);
-          const double ur = ua / dd;
-          zi[c * LDZ] += wd * (TN)ua * y;
-          lap += (w2 * (TN)(ur * ur) + wd * (TN)(1.0 - ur * ur)) * y;
+          const TN ua = gn[al];
+          const TN ur = ua * gn[3];
+          zi[c * LDZ] += wd * ua * y;
+          lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
         }
       }
       zi[LC * LDZ] = lap;
@@ -347,10 +365,16 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
     __syncthreads();
   }
   double* jt = jtan + ((int64_t)w * n_chunks + chunk) * (T + 1);
-  for (int col = threadIdx.x; col < C; col += blockDim.x) {
-    TN acc = 0;
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
-    jt[col == LC ? T : col] = (double)acc;
+  {
+    // one wavefront per column: dot product with the output weights
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
+      TN acc = 0;
+      for (int x = lane; x < DX; x += 64)
+        acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) jt[col == LC ? T : col] = (double)acc;
+    }
   }
   // ---- backflow head ----
   gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
@@ -377,13 +401,12 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent(Dims d, DevTables t, i
       __syncthreads();
     }
   }
+  gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+  __syncthreads();
   double* ft = ftan + ((int64_t)w * n_chunks + chunk) * N * (T + 1) * M;
   for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
     int row = q / M, mu = q % M, i = row / C, col = row % C;
-    TN acc = 0;
-    const TN* xr = XT + (size_t)row * LDX;
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(xr[x], bf16) * maybe_bf16(P[pl.kW3 + x * M + mu], bf16);
-    ft[((int64_t)i * (T + 1) + (col == LC ? T : col)) * M + mu] = (double)acc;
+    ft[((int64_t)i * (T + 1) + (col == LC ? T : col)) * M + mu] = (double)KT[(size_t)row * LDX + mu];
   }
 }
 
@@ -423,8 +446,10 @@ template <typename TN>
 size_t tangent_lds_bytes(const Dims& d, int T) {
   const int C = T + 1, R = d.N * C;
   const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
+  const int NCE = std::min(d.N, T / 3 + 2);  // electrons a chunk of T coordinates can touch
   return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
-         ((size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX) * sizeof(TN);
+         ((size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX + (size_t)NCE * (d.N + d.NN) * 4) *
+             sizeof(TN);
 }
 template <typename TN>
 size_t value_lds_bytes(const Dims& d, int wpb) {

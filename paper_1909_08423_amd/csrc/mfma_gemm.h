@@ -104,8 +104,8 @@ struct MfmaChain<float, KQ> {
 };
 
 template <typename TN, int KQ>
-__device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int O, TN* Y,
-                                            int ldy, bool accumulate, bool bf16) {
+__device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int ldw, int O,
+                                            int ncol, TN* Y, int ldy, bool accumulate, bool bf16) {
   typedef typename MfmaTile<TN>::acc_t acc_t;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
@@ -124,9 +124,10 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
   }
   for (int ct = ct0; ct < n_ct; ct += ct_step) {
     const int col = (ct << 4) + c16;
+    const bool colok = col < ncol;
     TN bfrag[KQ];
 #pragma unroll
-    for (int s = 0; s < KQ; ++s) bfrag[s] = W[(size_t)(g * KQ + s) * O + col];
+    for (int s = 0; s < KQ; ++s) bfrag[s] = colok ? W[(size_t)(g * KQ + s) * ldw + col] : TN(0);
     for (int rt = rt0; rt < n_rt; rt += rt_step) {
       const int r = min((rt << 4) + c16, rows - 1);
       const TN* xr = X + (size_t)r * ldx + g * KQ;
@@ -137,13 +138,13 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-        c[v] = (accumulate && row < rows) ? Y[(size_t)row * ldy + col] : TN(0);
+        c[v] = (accumulate && row < rows && colok) ? Y[(size_t)row * ldy + col] : TN(0);
       }
       c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-        if (row < rows) Y[(size_t)row * ldy + col] = c[v];
+        if (row < rows && colok) Y[(size_t)row * ldy + col] = c[v];
       }
     }
   }
@@ -151,14 +152,29 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 
 // Whole-block product; every thread of the block must call it.  I must be
 // one of 16, 32, 64, 128; O a multiple of 16.
+// Narrow output: W is [I][ncol] (row stride ncol), the product is computed
+// on ceil(ncol / 16) column tiles and only the ncol valid columns are
+// stored (used for the backflow output layer, ncol = number of orbitals).
+template <typename TN>
+__device__ __forceinline__ void gemm_mfma_cols(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W,
+                                               int ncol, TN* Y, int ldy, bool accumulate, bool bf16) {
+  const int O = (ncol + 15) & ~15;
+  switch (I) {
+    case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
+    case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
+    case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
+    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
+  }
+}
+
 template <typename TN>
 __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W, int O,
                                           TN* Y, int ldy, bool accumulate, bool bf16) {
   switch (I) {
-    case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
-    case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
-    case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
-    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, O, Y, ldy, accumulate, bf16); break;
+    case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
   }
 }
 

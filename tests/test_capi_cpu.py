@@ -74,15 +74,18 @@ def test_status_strings_and_argument_validation():
     s.det_up = arr([0], np.int32)
     s.det_down = arr([0], np.int32)
     s.ci = arr([1.0], np.float64)
-    n.n_feat, n.feat_cutoff, n.dim_x, n.dim_z, n.n_layers = 4, 10.0, 8, 4, 1
+    n.n_feat, n.feat_cutoff, n.dim_x, n.dim_z, n.n_layers = 16, 10.0, 16, 16, 1
     assert lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)) == 2
     # out-of-range determinant orbital index
     s.shell_l = arr([0], np.int32)
     s.det_up = arr([3], np.int32)
     assert lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)) == 1
-    # too many layers
+    # too many layers; widths the matrix-core products do not take
     s.det_up = arr([0], np.int32)
     n.n_layers = 99
+    assert lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)) == 2
+    n.n_layers = 1
+    n.dim_x = 48
     assert lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)) == 2
     # a null context is an invalid argument for every call
     assert lib.pn_eval(None, None, 1, None, None, 0, None, None, None, None, None, None, 0) == 1
