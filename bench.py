@@ -59,7 +59,7 @@ def chunk_T(s, net, prec):
     LDHZ = max(2 * LDZ, LDX)
     for nc in range(1, 3 * N + 1):
         T = -(-3 * N // nc)
-        if T > 15:
+        if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
             continue
         C = T + 1
         R = N * C

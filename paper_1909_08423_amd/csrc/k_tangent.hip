@@ -1,0 +1,354 @@
+// Tangent pass of the network: first derivatives and partial Laplacian of
+// every electron embedding, the Jastrow factor and the backflow, with
+// respect to one chunk of electron coordinates (Methods, "PauliNet
+// extension of SchNet"; Results, J = eta(sum_i x_i), f_i = kappa(x_i)).
+//
+// One block per (walker, chunk).  The chunk holds T = C - 1 coordinates
+// a = a0 .. a0 + T - 1 (the last chunk may be ragged; its missing
+// coordinates are zero columns).  For every electron row i the block keeps,
+// in LDS, the T derivative columns d x_i / d r_a and one column with
+// sum_{a in chunk} d^2 x_i / d r_a^2.  Each map is applied per coordinate,
+// so the chunks are independent and their partial Laplacians add up:
+//
+//   Linear  y = x W + b     ->  y_a = x_a W,        y_L = x_L W
+//   ssp     y = ssp(u)      ->  y_a = ssp'(u) u_a,  y_L = ssp'(u) u_L + ssp''(u) sum_a u_a^2
+//   message z_i = sum_j w_ij h_j  with w_ij = w(|r_i - r_j|):
+//           z_a = sum_j (w_ij h_{j,a} + d_a w_ij h_j)
+//           z_L = sum_j (w_ij h_{j,L} + sum_a (d2_a w_ij h_j + 2 d_a w_ij h_{j,a}))
+//     where, for a = (k, alpha) and u = r_i - r_j,
+//           d_a w_ij  = (w'/d) u_alpha (delta_ik - delta_jk)
+//           d2_a w_ij = w'' (u_alpha/d)^2 + (w'/d) (1 - (u_alpha/d)^2)   (k in {i, j})
+//
+// The values (h, w, w'/d, w'', ssp', ssp'') come from the value pass.  The
+// dense products run on the matrix cores (mfma_gemm.h); the message sums are
+// register-blocked over the C columns, which are a template parameter.
+#include "gemm_lds.h"
+#include "mfma_gemm.h"
+#include "pn_internal.h"
+
+namespace pn {
+
+constexpr int kThreadsT = 512;
+
+namespace {
+
+template <typename TN, int C>
+__global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
+                                                           const double* __restrict__ r, const TN* __restrict__ P,
+                                                           ParamLayout pl, const TN* __restrict__ filt,
+                                                           const TN* __restrict__ hval, const TN* __restrict__ kcoef,
+                                                           const TN* __restrict__ ecoef, double* __restrict__ ftan,
+                                                           double* __restrict__ jtan, bool bf16) {
+  constexpr int T = C - 1, LC = T;
+  extern __shared__ __align__(16) char smem[];
+  // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
+  const int64_t nb = (int64_t)gridDim.x;
+  const int64_t b = blockIdx.x;
+  int64_t task;
+  {
+    const int64_t per = nb / 8, rem = nb % 8;
+    const int64_t xcd = b % 8, slot = b / 8;
+    task = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + slot;
+  }
+  const int64_t w = task / n_chunks;
+  const int chunk = (int)(task % n_chunks);
+  if (w >= nw) return;
+  const int N = d.N, DX = d.DX, DZ = d.DZ, M = d.M, NU = d.n_up;
+  const int a0 = chunk * T;
+  const int Tc = min(T, 3 * N - a0);   // coordinates present in this chunk
+  const int R = N * C;                  // rows: (electron i, column)
+  const int e_lo = a0 / 3, e_hi = (a0 + Tc - 1) / 3;
+  const int NCE = e_hi - e_lo + 1;
+  const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDHZ = max(2 * LDZ, LDX);
+  double* rs = reinterpret_cast<double*>(smem);                 // [N][3]
+  int* pidx = reinterpret_cast<int*>(rs + 3 * kMaxElec);        // [N][N]
+  TN* hvs = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));   // [N][DZ]
+  TN* XT = hvs + N * DZ;                                        // [R][LDX]
+  TN* HT = XT + R * LDX;                                        // [R][LDZ]  (layers)
+  TN* ZT = HT + R * LDZ;                                        // [R][LDZ]  (layers)
+  TN* KT = HT;                                                  // [R][LDX]  (backflow head)
+  TN* ES = HT + R * LDHZ;                                       // [2][C][LDX]
+  TN* cg = ES + 2 * C * LDX;                                    // [NCE][N][4]  r_i - r_k, 1/|r_i - r_k|
+  TN* cgn = cg + NCE * N * 4;                                   // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
+  const double* rw = r + w * N * 3;
+  for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
+  for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
+  for (int q = threadIdx.x; q < R * LDX; q += blockDim.x) XT[q] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
+    const int k = e_lo + q / N, i = q % N;
+    const double ux = rs[3 * i] - rs[3 * k], uy = rs[3 * i + 1] - rs[3 * k + 1], uz = rs[3 * i + 2] - rs[3 * k + 2];
+    cg[4 * q + 0] = (TN)ux;
+    cg[4 * q + 1] = (TN)uy;
+    cg[4 * q + 2] = (TN)uz;
+    cg[4 * q + 3] = i == k ? TN(0) : (TN)(1.0 / sqrt(ux * ux + uy * uy + uz * uz));
+  }
+  for (int q = threadIdx.x; q < NCE * d.NN; q += blockDim.x) {
+    const int k = e_lo + q / d.NN, I = q % d.NN;
+    const double ux = rs[3 * k] - t.nuc_xyz[3 * I], uy = rs[3 * k + 1] - t.nuc_xyz[3 * I + 1],
+                 uz = rs[3 * k + 2] - t.nuc_xyz[3 * I + 2];
+    cgn[4 * q + 0] = (TN)ux;
+    cgn[4 * q + 1] = (TN)uy;
+    cgn[4 * q + 2] = (TN)uz;
+    cgn[4 * q + 3] = (TN)(1.0 / sqrt(ux * ux + uy * uy + uz * uz));
+  }
+  const int64_t fl_stride = (int64_t)3 * d.n_pairs * DZ;
+  for (int n = 0; n < d.L; ++n) {
+    const ParamLayout::Layer& Lp = pl.layer[n];
+    const TN* fw = filt + w * fl_stride * d.L + n * fl_stride;
+    const TN* fv = fw;                                 // w
+    const TN* fd = fw + (int64_t)d.n_pairs * DZ;       // w'/d
+    const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
+    const TN* hv = hval + (w * d.L + n) * N * DZ;
+    for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) hvs[q] = hv[q];
+    if (n > 0) gemm_mfma<TN>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
+    __syncthreads();
+    for (int ch = 0; ch < 2; ++ch) {
+      for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) {
+        const int i = q / DZ, z = q % DZ;
+        const bool up_i = i < NU;
+        // electrons of this channel: same spin (ch 0) or opposite spin (ch 1)
+        const bool want_up = (ch == 0) == up_i;
+        const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
+        TN acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0;
+        if (n > 0) {
+          for (int j = j_lo; j < j_hi; ++j) {
+            if (j == i) continue;
+            const TN wv = fv[(int64_t)pidx[i * N + j] * DZ + z];
+            const TN* hj = HT + (size_t)j * C * LDZ + z;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wv * hj[c * LDZ];
+          }
+        }
+        TN* zi = ZT + (size_t)i * C * LDZ + z;
+        TN lap = acc[LC];
+        // sources from the coordinates of electron i itself
+        if (i >= e_lo && i <= e_hi) {
+          const TN* gi = cg + (size_t)(i - e_lo) * N * 4;  // r_j - r_i
+          const int c0 = 3 * i - a0;
+          TN sv0 = 0, sv1 = 0, sv2 = 0;
+          for (int j = j_lo; j < j_hi; ++j) {
+            if (j == i) continue;
+            const int64_t p = pidx[i * N + j];
+            const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+            const TN hj = hvs[j * DZ + z];
+            const TN inv = gi[4 * j + 3];
+            const TN* hjc = HT + (size_t)j * C * LDZ + z;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+              const int c = c0 + al;
+              if (c < 0 || c >= Tc) continue;
+              const TN ua = -gi[4 * j + al];  // (r_i - r_j)_alpha
+              const TN ur = ua * inv;
+              const TN dw = wd * ua;
+              if (al == 0) sv0 += dw * hj;
+              if (al == 1) sv1 += dw * hj;
+              if (al == 2) sv2 += dw * hj;
+              lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hj;
+              if (n > 0) lap += TN(2) * dw * hjc[c * LDZ];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int al = c - c0;
+            if (al == 0) acc[c] += sv0;
+            if (al == 1) acc[c] += sv1;
+            if (al == 2) acc[c] += sv2;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < LC; ++c) zi[c * LDZ] = acc[c];
+        // sources from the coordinates of the chunk's other electrons k
+        for (int k = max(e_lo, j_lo); k <= min(e_hi, j_hi - 1); ++k) {
+          if (k == i) continue;
+          const int64_t p = pidx[i * N + k];
+          const TN* gk = cg + ((size_t)(k - e_lo) * N + i) * 4;  // r_i - r_k
+          const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+          const TN hk = hvs[k * DZ + z];
+          const TN* hkc = HT + (size_t)k * C * LDZ + z;
+#pragma unroll
+          for (int al = 0; al < 3; ++al) {
+            const int c = 3 * k + al - a0;
+            if (c < 0 || c >= Tc) continue;
+            const TN ua = gk[al];
+            const TN ur = ua * gk[3];
+            const TN dw = -wd * ua;  // d/dr_k of w(|r_i - r_k|)
+            zi[c * LDZ] += dw * hk;
+            lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hk;
+            if (n > 0) lap += TN(2) * dw * hkc[c * LDZ];
+          }
+        }
+        zi[LC * LDZ] = lap;
+      }
+      __syncthreads();
+      gemm_mfma<TN>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
+      __syncthreads();
+    }
+    // nuclear channel: only rows of the chunk's own electrons are non-zero
+    for (int q = threadIdx.x; q < NCE * DZ; q += blockDim.x) {
+      const int i = e_lo + q / DZ, z = q % DZ;
+      TN* zi = ZT + (size_t)i * C * LDZ + z;
+      TN acc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = 0;
+      const int c0 = 3 * i - a0;
+      for (int I = 0; I < d.NN; ++I) {
+        const int64_t p = d.n_ee + i * d.NN + I;
+        const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
+        const TN y = P[pl.Y + I * DZ + z];
+        const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+#pragma unroll
+        for (int c = 0; c < T; ++c) {
+          const int al = c - c0;
+          if (al < 0 || al > 2 || c >= Tc) continue;
+          const TN ua = gn[al];
+          const TN ur = ua * gn[3];
+          acc[c] += wd * ua * y;
+          acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) zi[c * LDZ] = acc[c];
+    }
+    __syncthreads();
+    gemm_mfma<TN>(ZT + (size_t)e_lo * C * LDZ, LDZ, NCE * C, DZ, P + Lp.gW[2], DX, XT + (size_t)e_lo * C * LDX, LDX,
+                  true, bf16);
+    __syncthreads();
+  }
+  // ---- Jastrow head on sum_i x_i, rows = columns ----
+  TN* S0 = ES;             // [C][LDX]
+  TN* S1 = ES + C * LDX;   // [C][LDX]
+  for (int q = threadIdx.x; q < C * DX; q += blockDim.x) {
+    const int col = q / DX, x = q % DX;
+    TN s = 0;
+    for (int i = 0; i < N; ++i) s += XT[((size_t)i * C + col) * LDX + x];
+    S0[col * LDX + x] = s;
+  }
+  __syncthreads();
+  for (int lay = 0; lay < 2; ++lay) {
+    TN* Sin = lay == 0 ? S0 : S1;
+    TN* Sout = lay == 0 ? S1 : S0;
+    gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
+    __syncthreads();
+    const TN* ec = ecoef + (w * 2 + lay) * 2 * DX;
+    for (int x = threadIdx.x; x < DX; x += blockDim.x) {
+      const TN s1 = ec[x], s2 = ec[DX + x];
+      TN sq = 0;
+#pragma unroll
+      for (int col = 0; col < LC; ++col) {
+        const TN v = Sout[col * LDX + x];
+        sq += v * v;
+        Sout[col * LDX + x] = s1 * v;
+      }
+      Sout[LC * LDX + x] = s1 * Sout[LC * LDX + x] + s2 * sq;
+    }
+    __syncthreads();
+  }
+  double* jt = jtan + ((int64_t)w * n_chunks + chunk) * C;
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
+      TN acc = 0;
+      for (int x = lane; x < DX; x += 64)
+        acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) jt[col] = (double)acc;
+    }
+  }
+  // ---- backflow head ----
+  gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
+  __syncthreads();
+  for (int lay = 0; lay < 2; ++lay) {
+    TN* A = lay == 0 ? KT : XT;
+    const TN* kc = kcoef + (w * 2 + lay) * 2 * N * DX;
+    for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
+      const int i = q / DX, x = q % DX;
+      const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
+      TN sq = 0;
+      TN* ai = A + (size_t)i * C * LDX + x;
+#pragma unroll
+      for (int col = 0; col < LC; ++col) {
+        const TN v = ai[col * LDX];
+        sq += v * v;
+        ai[col * LDX] = s1 * v;
+      }
+      ai[LC * LDX] = s1 * ai[LC * LDX] + s2 * sq;
+    }
+    __syncthreads();
+    if (lay == 0) {
+      gemm_mfma<TN>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+      __syncthreads();
+    }
+  }
+  gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+  __syncthreads();
+  double* ft = ftan + ((int64_t)w * n_chunks + chunk) * N * C * M;
+  for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
+    const int row = q / M, mu = q % M;
+    ft[(int64_t)row * M + mu] = (double)KT[(size_t)row * LDX + mu];
+  }
+}
+
+template <typename TN, int C>
+void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
+              bool bf16) {
+  const int64_t nb = nw * L.n_chunks;
+  if (L.lds_tangent > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_net_tangent<TN, C>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_tangent);
+  hipLaunchKernelGGL((k_net_tangent<TN, C>), dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d, c->t, nw,
+                     L.n_chunks, r, P, c->pl, reinterpret_cast<const TN*>(ws + L.filt),
+                     reinterpret_cast<const TN*>(ws + L.hval), reinterpret_cast<const TN*>(ws + L.kcoef),
+                     reinterpret_cast<const TN*>(ws + L.ecoef), reinterpret_cast<double*>(ws + L.ftan),
+                     reinterpret_cast<double*>(ws + L.jtan), bf16);
+}
+
+}  // namespace
+
+// Chunk sizes T the kernel is instantiated for (columns C = T + 1).
+bool tangent_chunk_supported(int T) {
+  switch (T) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 9: case 10: case 12: case 15: return true;
+    default: return false;
+  }
+}
+
+template <typename TN>
+size_t tangent_lds_bytes(const Dims& d, int T) {
+  const int C = T + 1, R = d.N * C;
+  const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
+  const int NCE = std::min(d.N, T / 3 + 2);  // electrons a chunk of T coordinates can touch
+  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
+         ((size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX + (size_t)NCE * (d.N + d.NN) * 4) *
+             sizeof(TN);
+}
+
+template <typename TN>
+void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                        const WsLayout& L, bool bf16) {
+  switch (L.T + 1) {
+    case 2: launch_c<TN, 2>(c, s, nw, r, P, ws, L, bf16); break;
+    case 3: launch_c<TN, 3>(c, s, nw, r, P, ws, L, bf16); break;
+    case 4: launch_c<TN, 4>(c, s, nw, r, P, ws, L, bf16); break;
+    case 5: launch_c<TN, 5>(c, s, nw, r, P, ws, L, bf16); break;
+    case 6: launch_c<TN, 6>(c, s, nw, r, P, ws, L, bf16); break;
+    case 7: launch_c<TN, 7>(c, s, nw, r, P, ws, L, bf16); break;
+    case 9: launch_c<TN, 9>(c, s, nw, r, P, ws, L, bf16); break;
+    case 10: launch_c<TN, 10>(c, s, nw, r, P, ws, L, bf16); break;
+    case 11: launch_c<TN, 11>(c, s, nw, r, P, ws, L, bf16); break;
+    case 13: launch_c<TN, 13>(c, s, nw, r, P, ws, L, bf16); break;
+    case 16: launch_c<TN, 16>(c, s, nw, r, P, ws, L, bf16); break;
+    default: break;  // the planner only picks supported chunk sizes
+  }
+}
+
+template size_t tangent_lds_bytes<double>(const Dims&, int);
+template size_t tangent_lds_bytes<float>(const Dims&, int);
+template void launch_net_tangent<double>(const pn_ctx*, hipStream_t, int64_t, const double*, const double*, char*,
+                                         const WsLayout&, bool);
+template void launch_net_tangent<float>(const pn_ctx*, hipStream_t, int64_t, const double*, const float*, char*,
+                                        const WsLayout&, bool);
+
+}  // namespace pn

@@ -151,7 +151,10 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 }
 
 // Whole-block product; every thread of the block must call it.  I must be
-// one of 16, 32, 64, 128; O a multiple of 16.
+// one of 16, 32, 64, 128 (128 runs as two accumulated halves of 64, which
+// keeps at most 16 operand fragments live per lane); O a multiple of 16.
+// The caller separates the halves' read and write of Y with nothing: each
+// output element is owned by one lane in both halves.
 // Narrow output: W is [I][ncol] (row stride ncol), the product is computed
 // on ceil(ncol / 16) column tiles and only the ncol valid columns are
 // stored (used for the backflow output layer, ncol = number of orbitals).
@@ -163,7 +166,10 @@ __device__ __forceinline__ void gemm_mfma_cols(const TN* X, int ldx, int rows, i
     case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
     case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
     case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
-    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16); break;
+    default:
+      gemm_mfma_k<TN, 16>(X, ldx, rows, W, ncol, O, ncol, Y, ldy, accumulate, bf16);
+      gemm_mfma_k<TN, 16>(X + 64, ldx, rows, W + (size_t)64 * ncol, ncol, O, ncol, Y, ldy, true, bf16);
+      break;
   }
 }
 
@@ -174,7 +180,10 @@ __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I,
     case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
     case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
     case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    default: gemm_mfma_k<TN, 32>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    default:
+      gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
+      gemm_mfma_k<TN, 16>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      break;
   }
 }
 

@@ -18,7 +18,7 @@ size_t value_lds_bytes(const Dims& d, int wpb);
 size_t slater_tangent_lds_bytes(const Dims& d, int T);
 template <typename TN>
 size_t filter_lds_bytes(const Dims& d, int PT);
-constexpr int kMaxChunk = 15;  // coordinates per tangent chunk (columns T + 1 <= 16)
+bool tangent_chunk_supported(int T);
 void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
                      bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params);
 size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32);
@@ -129,7 +129,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   L.T = 1;
   for (int nc = 1; nc <= ncoord; ++nc) {
     int T = (ncoord + nc - 1) / nc;
-    if (T > kMaxChunk) continue;
+    if (!tangent_chunk_supported(T)) continue;
     size_t lds = fp64 ? tangent_lds_bytes<double>(d, T) : tangent_lds_bytes<float>(d, T);
     if (lds <= budget || T == 1) {
       L.T = T;
