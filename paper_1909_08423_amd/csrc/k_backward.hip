@@ -1,16 +1,533 @@
-// Value-path adjoint of ln|psi| with respect to the network parameters.
+// Value-path adjoint: grad_theta += sum_w ct_w d ln|psi_w| / d theta.
+//
+// The Hermitian gradient estimator (Methods, eq. "trainig") needs only the
+// parameter gradient of ln|psi| weighted per walker by 2 (E_loc - L) / B,
+// which is this adjoint with ct_w = that weight.  ln|psi| = gamma + J +
+// ln|Psi_d| depends on theta through J and through the backflow f inside
+// the determinants:
+//   d ln|Psi_d| / d A_p^s[k][i] = w_p (A_p^s)^{-1}[i][k],  w_p = c_p D_p / Psi_d
+//   A_p^s[k][i] = phi_mu(r_i) f_{i mu},  mu = mu_p^s(k)
+// so  d ln|psi| / d f_{i mu} = phi_mu(r_i) sum_p w_p sum_{k: mu_p(k) = mu} G_p[i][k].
+// From there the reverse sweep runs through kappa, eta, the interaction
+// layers (messages, h and the three g) and finally the filter networks.
+//
+// Kernels (the forward values come from the value pass, run just before):
+//  k_bwd_net     groups of WB walkers; grid-stride over groups with a fixed
+//                grid, each block summing its parameter gradients into its
+//                own slot; writes the cotangents of the filter outputs.
+//  k_bwd_filter  per (layer, channel) and a fixed set of blocks striding
+//                over (walker, pair) rows; recomputes features and the
+//                hidden layer, accumulates the filter gradients in registers.
+//  k_bwd_reduce  sums the slots in a fixed order into the FP64 gradient.
+// The fixed grids and slot order make the result independent of anything
+// else running on the device.
+#include "gemm_lds.h"
+#include "mfma_gemm.h"
 #include "pn_internal.h"
 
 namespace pn {
+namespace {
+
+constexpr int kSlotsNet = 512;     // blocks (and gradient slots) of k_bwd_net
+constexpr int kSlotsFilter = 256;  // blocks per (layer, channel) of k_bwd_filter
+constexpr int kFiltRows = 32;      // (walker, pair) rows per tile of k_bwd_filter
+
+template <typename TN>
+__device__ __forceinline__ TN sig(TN u) {
+  return sigmoid_d(u);
+}
+
+// slot[a*B + b] (+)= sum_r X[r][a] Y[r][b]
+template <typename TN>
+__device__ void outer_acc(const TN* X, int ldx, int A, const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
+  for (int q = threadIdx.x; q < A * B; q += blockDim.x) {
+    const int a = q / B, b = q % B;
+    TN s = 0;
+    for (int r = 0; r < rows; ++r) s += X[(size_t)r * ldx + a] * Y[(size_t)r * ldy + b];
+    slot[q] = first ? s : slot[q] + s;
+  }
+}
+// same with X replaced by ssp(U) (recomputed on the fly)
+template <typename TN>
+__device__ void outer_acc_ssp(const TN* U, int ldu, int A, const TN* Y, int ldy, int B, int rows, TN* slot,
+                              bool first) {
+  for (int q = threadIdx.x; q < A * B; q += blockDim.x) {
+    const int a = q / B, b = q % B;
+    TN s = 0;
+    for (int r = 0; r < rows; ++r) s += ssp(U[(size_t)r * ldu + a]) * Y[(size_t)r * ldy + b];
+    slot[q] = first ? s : slot[q] + s;
+  }
+}
+// slot[b] (+)= sum_r Y[r][b]
+template <typename TN>
+__device__ void colsum_acc(const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    TN s = 0;
+    for (int r = 0; r < rows; ++r) s += Y[(size_t)r * ldy + b];
+    slot[b] = first ? s : slot[b] + s;
+  }
+}
+
+template <typename TN>
+__global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64_t nw, int WB,
+                                                      const TN* __restrict__ P, ParamLayout pl,
+                                                      const TN* __restrict__ xval, const TN* __restrict__ hval,
+                                                      const TN* __restrict__ filt, const double* __restrict__ phi,
+                                                      const double* __restrict__ ginv, const double* __restrict__ wdet,
+                                                      const double* __restrict__ ct_logabs, TN* __restrict__ ctw,
+                                                      TN* __restrict__ gslot, int64_t n_params) {
+  extern __shared__ __align__(16) char smem[];
+  const int N = d.N, DX = d.DX, DZ = d.DZ, M = d.M, L = d.L, NU = d.n_up;
+  const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDM = ld_pad<TN>((M + 15) & ~15);
+  const int RW = WB * N;
+  TN* slot = gslot + (size_t)blockIdx.x * n_params;
+  int* pidx = reinterpret_cast<int*>(smem);
+  TN* cw = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));  // [WB]
+  TN* X = cw + ((WB + 3) & ~3);                                 // [RW][LDX]
+  TN* CX = X + RW * LDX;                                        // [RW][LDX]
+  TN* UN = CX + RW * LDX;                                       // union region
+  // heads view
+  TN* A = UN;                  // [RW][LDX]
+  TN* B = A + RW * LDX;        // [RW][LDX]
+  TN* Cb = B + RW * LDX;       // [RW][LDX]
+  TN* CF = Cb + RW * LDX;      // [RW][LDM]
+  // layers view
+  TN* H = UN;                  // [RW][LDZ]
+  TN* Z = H + RW * LDZ;
+  TN* CZ = Z + RW * LDZ;
+  TN* CH = CZ + RW * LDZ;
+  const int64_t fl_stride = (int64_t)3 * d.n_pairs * DZ;
+  const int64_t ng = (nw + WB - 1) / WB;
+  for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
+  bool first = true;
+  for (int64_t grp = blockIdx.x; grp < ng; grp += gridDim.x, first = false) {
+    const int64_t w0 = grp * WB;
+    const int nwb = (int)min((int64_t)WB, nw - w0);
+    const int R = nwb * N;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nwb; q += blockDim.x) cw[q] = (TN)ct_logabs[w0 + q];
+    // ---- cotangent of the backflow, from the determinants ----
+    for (int q = threadIdx.x; q < R * LDM; q += blockDim.x) CF[q] = 0;
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
+      X[(q / DX) * LDX + q % DX] = xval[((w0 + q / (N * DX)) * (L + 1) + L) * N * DX + q % (N * DX)];
+    __syncthreads();
+    const int gsz = d.n_up * d.n_up + d.n_dn * d.n_dn;
+    for (int row = threadIdx.x; row < R; row += blockDim.x) {
+      const int wl = row / N, i = row % N;
+      const int64_t w = w0 + wl;
+      const bool up = i < NU;
+      const int n = up ? d.n_up : d.n_dn, ii = up ? i : i - NU;
+      const int* dets = up ? t.det_up : t.det_dn;
+      for (int p = 0; p < d.P; ++p) {
+        const double wp = wdet[w * d.P + p];
+        const double* G = ginv + (w * d.P + p) * gsz + (up ? 0 : d.n_up * d.n_up);
+        for (int k = 0; k < n; ++k) CF[row * LDM + dets[p * n + k]] += (TN)(wp * G[ii * n + k]);
+      }
+      const double* ph = phi + (w * N + i) * M * 7;
+      for (int mu = 0; mu < M; ++mu) CF[row * LDM + mu] *= (TN)(ph[mu * 7]) * cw[wl];
+    }
+    __syncthreads();
+    // ---- Jastrow head (per walker): J = eta(sum_i x_i) ----
+    {
+      TN* Sv = CF + RW * LDM;  // [WB][LDX] s
+      TN* U1 = Sv + WB * LDX;  // pre-activations
+      TN* U2 = U1 + WB * LDX;
+      TN* Y1 = U2 + WB * LDX;
+      TN* C1 = Y1 + WB * LDX;  // cotangents
+      TN* C2 = C1 + WB * LDX;
+      for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
+        const int wl = q / DX, x = q % DX;
+        TN s = 0;
+        for (int i = 0; i < N; ++i) s += X[(wl * N + i) * LDX + x];
+        Sv[wl * LDX + x] = s;
+      }
+      __syncthreads();
+      gemm_mfma<TN>(Sv, LDX, nwb, DX, P + pl.eW1, DX, U1, LDX, false, false);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
+        const int r = q / DX, x = q % DX;
+        U1[r * LDX + x] += P[pl.eb1 + x];
+        Y1[r * LDX + x] = ssp(U1[r * LDX + x]);
+      }
+      __syncthreads();
+      gemm_mfma<TN>(Y1, LDX, nwb, DX, P + pl.eW2, DX, U2, LDX, false, false);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
+        const int r = q / DX, x = q % DX;
+        U2[r * LDX + x] += P[pl.eb2 + x];
+        // d/d u2 = cJ * W3[x] * ssp'(u2)
+        C2[r * LDX + x] = cw[r] * P[pl.eW3 + x] * sig(U2[r * LDX + x]);
+      }
+      __syncthreads();
+      // dW3, db3
+      for (int x = threadIdx.x; x < DX; x += blockDim.x) {
+        TN s = 0;
+        for (int r = 0; r < nwb; ++r) s += ssp(U2[r * LDX + x]) * cw[r];
+        slot[pl.eW3 + x] = first ? s : slot[pl.eW3 + x] + s;
+      }
+      if (threadIdx.x == 0) {
+        TN s = 0;
+        for (int r = 0; r < nwb; ++r) s += cw[r];
+        slot[pl.eb3] = first ? s : slot[pl.eb3] + s;
+      }
+      outer_acc_ssp<TN>(U1, LDX, DX, C2, LDX, DX, nwb, slot + pl.eW2, first);
+      colsum_acc<TN>(C2, LDX, DX, nwb, slot + pl.eb2, first);
+      gemm_mfma_wt<TN>(C2, LDX, nwb, DX, P + pl.eW2, DX, C1, LDX, false);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
+        const int r = q / DX, x = q % DX;
+        C1[r * LDX + x] *= sig(U1[r * LDX + x]);
+      }
+      __syncthreads();
+      outer_acc<TN>(Sv, LDX, DX, C1, LDX, DX, nwb, slot + pl.eW1, first);
+      colsum_acc<TN>(C1, LDX, DX, nwb, slot + pl.eb1, first);
+      gemm_mfma_wt<TN>(C1, LDX, nwb, DX, P + pl.eW1, DX, C2, LDX, false);  // d/d s
+      __syncthreads();
+      for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
+        const int row = q / DX, x = q % DX;
+        CX[row * LDX + x] = C2[(row / N) * LDX + x];
+      }
+      __syncthreads();
+    }
+    // ---- backflow head: f = 1 + kappa(x_i) ----
+    gemm_mfma<TN>(X, LDX, R, DX, P + pl.kW1, DX, A, LDX, false, false);
+    __syncthreads();
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
+      const int r = q / DX, x = q % DX;
+      A[r * LDX + x] += P[pl.kb1 + x];
+      B[r * LDX + x] = ssp(A[r * LDX + x]);
+    }
+    __syncthreads();
+    gemm_mfma<TN>(B, LDX, R, DX, P + pl.kW2, DX, Cb, LDX, false, false);
+    __syncthreads();
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) Cb[(q / DX) * LDX + q % DX] += P[pl.kb2 + q % DX];
+    __syncthreads();
+    outer_acc_ssp<TN>(Cb, LDX, DX, CF, LDM, M, R, slot + pl.kW3, first);
+    colsum_acc<TN>(CF, LDM, M, R, slot + pl.kb3, first);
+    // d/d y2 = CF W3^T  (W3 is [DX][M]; rows of the transposed product are M long)
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
+      const int r = q / DX, x = q % DX;
+      TN s = 0;
+      for (int mu = 0; mu < M; ++mu) s += CF[r * LDM + mu] * P[pl.kW3 + x * M + mu];
+      B[r * LDX + x] = s * sig(Cb[r * LDX + x]);  // d/d u2
+    }
+    __syncthreads();
+    outer_acc_ssp<TN>(A, LDX, DX, B, LDX, DX, R, slot + pl.kW2, first);
+    colsum_acc<TN>(B, LDX, DX, R, slot + pl.kb2, first);
+    gemm_mfma_wt<TN>(B, LDX, R, DX, P + pl.kW2, DX, Cb, LDX, false);
+    __syncthreads();
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
+      const int r = q / DX, x = q % DX;
+      Cb[r * LDX + x] *= sig(A[r * LDX + x]);  // d/d u1
+    }
+    __syncthreads();
+    outer_acc<TN>(X, LDX, DX, Cb, LDX, DX, R, slot + pl.kW1, first);
+    colsum_acc<TN>(Cb, LDX, DX, R, slot + pl.kb1, first);
+    gemm_mfma_wt<TN>(Cb, LDX, R, DX, P + pl.kW1, DX, CX, LDX, true);
+    __syncthreads();
+    // ---- interaction layers, last to first ----
+    for (int n = L - 1; n >= 0; --n) {
+      const ParamLayout::Layer& Lp = pl.layer[n];
+      for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
+        X[(q / DX) * LDX + q % DX] = xval[((w0 + q / (N * DX)) * (L + 1) + n) * N * DX + q % (N * DX)];
+      for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
+        H[(q / DZ) * LDZ + q % DZ] = hval[((w0 + q / (N * DZ)) * L + n) * N * DZ + q % (N * DZ)];
+        CH[(q / DZ) * LDZ + q % DZ] = 0;
+      }
+      __syncthreads();
+      for (int ch = 0; ch < 3; ++ch) {
+        // recompute the messages of this channel
+        for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
+          const int row = q / DZ, z = q % DZ, wl = row / N, i = row % N;
+          const TN* fv = filt + (w0 + wl) * fl_stride * L + n * fl_stride;
+          TN acc = 0;
+          if (ch < 2) {
+            const bool want_up = (ch == 0) == (i < NU);
+            for (int j = want_up ? 0 : NU; j < (want_up ? NU : N); ++j) {
+              if (j == i) continue;
+              acc += fv[(int64_t)pidx[i * N + j] * DZ + z] * H[(wl * N + j) * LDZ + z];
+            }
+          } else {
+            for (int I = 0; I < d.NN; ++I) acc += fv[(int64_t)(d.n_ee + i * d.NN + I) * DZ + z] * P[pl.Y + I * DZ + z];
+          }
+          Z[row * LDZ + z] = acc;
+        }
+        __syncthreads();
+        outer_acc<TN>(Z, LDZ, DZ, CX, LDX, DX, R, slot + Lp.gW[ch], first);
+        colsum_acc<TN>(CX, LDX, DX, R, slot + Lp.gb[ch], first);
+        gemm_mfma_wt<TN>(CX, LDX, R, DX, P + Lp.gW[ch], DZ, CZ, LDZ, false);  // d/d z
+        __syncthreads();
+        if (ch < 2) {
+          // d/d h_j += sum_i w_ij d/d z_i ; filter cotangent per pair
+          for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
+            const int row = q / DZ, z = q % DZ, wl = row / N, j = row % N;
+            const TN* fv = filt + (w0 + wl) * fl_stride * L + n * fl_stride;
+            const bool want_up = (ch == 0) == (j < NU);
+            TN acc = 0;
+            for (int i = want_up ? 0 : NU; i < (want_up ? NU : N); ++i) {
+              if (i == j) continue;
+              acc += fv[(int64_t)pidx[i * N + j] * DZ + z] * CZ[(wl * N + i) * LDZ + z];
+            }
+            CH[row * LDZ + z] += acc;
+          }
+          const int p_lo = ch == 0 ? 0 : (d.n_up * (d.n_up - 1) + d.n_dn * (d.n_dn - 1)) / 2;
+          const int p_hi = ch == 0 ? p_lo + (d.n_up * (d.n_up - 1) + d.n_dn * (d.n_dn - 1)) / 2 : d.n_ee;
+          for (int q = threadIdx.x; q < nwb * (p_hi - p_lo) * DZ; q += blockDim.x) {
+            const int wl = q / ((p_hi - p_lo) * DZ), rem = q % ((p_hi - p_lo) * DZ);
+            const int p = p_lo + rem / DZ, z = rem % DZ;
+            const int i = t.pair_ij[2 * p], j = t.pair_ij[2 * p + 1];
+            const TN v = CZ[(wl * N + i) * LDZ + z] * H[(wl * N + j) * LDZ + z] +
+                         CZ[(wl * N + j) * LDZ + z] * H[(wl * N + i) * LDZ + z];
+            ctw[(((w0 + wl) * L + n) * d.n_pairs + p) * DZ + z] = v;
+          }
+        } else {
+          for (int q = threadIdx.x; q < nwb * N * d.NN * DZ; q += blockDim.x) {
+            const int wl = q / (N * d.NN * DZ), rem = q % (N * d.NN * DZ);
+            const int i = rem / (d.NN * DZ), I = (rem / DZ) % d.NN, z = rem % DZ;
+            const int p = d.n_ee + i * d.NN + I;
+            ctw[(((w0 + wl) * L + n) * d.n_pairs + p) * DZ + z] = CZ[(wl * N + i) * LDZ + z] * P[pl.Y + I * DZ + z];
+          }
+          {
+            // d/d Y_I = sum over layers and electrons of w_iI d/d z_i (this layer's share)
+            for (int q = threadIdx.x; q < d.NN * DZ; q += blockDim.x) {
+              const int I = q / DZ, z = q % DZ;
+              TN s = 0;
+              for (int row = 0; row < R; ++row) {
+                const int wl = row / N, i = row % N;
+                const TN* fv = filt + (w0 + wl) * fl_stride * L + n * fl_stride;
+                s += fv[(int64_t)(d.n_ee + i * d.NN + I) * DZ + z] * CZ[row * LDZ + z];
+              }
+              const bool wr = first && n == L - 1;
+              slot[pl.Y + q] = wr ? s : slot[pl.Y + q] + s;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // h = x W_h + b_h
+      outer_acc<TN>(X, LDX, DX, CH, LDZ, DZ, R, slot + Lp.hW, first);
+      colsum_acc<TN>(CH, LDZ, DZ, R, slot + Lp.hb, first);
+      gemm_mfma_wt<TN>(CH, LDZ, R, DZ, P + Lp.hW, DX, CX, LDX, true);
+      __syncthreads();
+    }
+    // x^(0) = x0 for every electron
+    colsum_acc<TN>(CX, LDX, DX, R, slot + pl.x0, first);
+  }
+}
+
+template <typename TN>
+__global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, int64_t nw, const double* __restrict__ r,
+                                                         const TN* __restrict__ P, ParamLayout pl,
+                                                         const TN* __restrict__ ctw, TN* __restrict__ fslot,
+                                                         int n_same) {
+  extern __shared__ __align__(16) char smem[];
+  const int layer = blockIdx.y / 3, ch = blockIdx.y % 3;
+  const int K = d.K, DZ = d.DZ, L = d.L;
+  const int LDK = ld_pad<TN>(K), LDZ = ld_pad<TN>(DZ);
+  const int PT = kFiltRows;
+  const int p_lo = ch == 0 ? 0 : (ch == 1 ? n_same : d.n_ee);
+  const int p_hi = ch == 0 ? n_same : (ch == 1 ? d.n_ee : d.n_pairs);
+  const int np = p_hi - p_lo;
+  const int64_t nrows = nw * np;
+  double* dd = reinterpret_cast<double*>(smem);  // [PT]
+  TN* E = reinterpret_cast<TN*>(dd + PT);        // [PT][LDK] features
+  TN* U = E + PT * LDK;                          // [PT][LDZ] pre-activation of the hidden layer
+  TN* CW = U + PT * LDZ;                         // [PT][LDZ] d/d w
+  TN* CU = CW + PT * LDZ;                        // [PT][LDZ] d/d u
+  const ParamLayout::Layer& Lp = pl.layer[layer];
+  const int fsz = K * DZ + DZ + DZ * DZ + DZ;
+  // gradient accumulators owned by this thread: indices q = tid + k * blockDim
+  constexpr int kAcc = 32;  // fsz <= kAcc * kThreads  (K, DZ <= 64 -> fsz <= 8320)
+  TN acc[kAcc];
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) acc[k] = 0;
+  for (int64_t row0 = (int64_t)blockIdx.x * PT; row0 < nrows; row0 += (int64_t)gridDim.x * PT) {
+    const int rows = (int)min((int64_t)PT, nrows - row0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < PT; q += blockDim.x) {
+      double v = 1.0;
+      if (q < rows) {
+        const int64_t g = row0 + q, w = g / np;
+        const int p = p_lo + (int)(g % np);
+        const double* rw = r + w * d.N * 3;
+        double x, y, z;
+        if (p < d.n_ee) {
+          const int i = t.pair_ij[2 * p], j = t.pair_ij[2 * p + 1];
+          x = rw[3 * i] - rw[3 * j];
+          y = rw[3 * i + 1] - rw[3 * j + 1];
+          z = rw[3 * i + 2] - rw[3 * j + 2];
+        } else {
+          const int q2 = p - d.n_ee, i = q2 / d.NN, I = q2 % d.NN;
+          x = rw[3 * i] - t.nuc_xyz[3 * I];
+          y = rw[3 * i + 1] - t.nuc_xyz[3 * I + 1];
+          z = rw[3 * i + 2] - t.nuc_xyz[3 * I + 2];
+        }
+        v = sqrt(x * x + y * y + z * z);
+      }
+      dd[q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < PT * K; q += blockDim.x) {
+      const int row = q / K, k = q % K;
+      TN e = 0;
+      if (row < rows) {
+        const double dv = dd[row], dm = dv - t.feat_mu[k];
+        e = (TN)(dv * dv * exp(-dv - dm * dm * t.feat_sig2inv[k]));
+      }
+      E[row * LDK + k] = e;
+    }
+    for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) {
+      const int row = q / DZ, z = q % DZ;
+      TN v = 0;
+      if (row < rows) {
+        const int64_t g = row0 + row, w = g / np;
+        const int p = p_lo + (int)(g % np);
+        v = ctw[((w * L + layer) * d.n_pairs + p) * DZ + z];
+      }
+      CW[row * LDZ + z] = v;
+    }
+    __syncthreads();
+    gemm_mfma<TN>(E, LDK, PT, K, P + Lp.w1W[ch], DZ, U, LDZ, false, false);
+    __syncthreads();
+    for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) U[(q / DZ) * LDZ + q % DZ] += P[Lp.w1b[ch] + q % DZ];
+    __syncthreads();
+    gemm_mfma_wt<TN>(CW, LDZ, PT, DZ, P + Lp.w2W[ch], DZ, CU, LDZ, false);
+    __syncthreads();
+    for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) {
+      const int row = q / DZ, z = q % DZ;
+      CU[row * LDZ + z] = row < rows ? CU[row * LDZ + z] * sig(U[row * LDZ + z]) : TN(0);
+    }
+    __syncthreads();
+    // accumulate: [w1W K x DZ][w1b DZ][w2W DZ x DZ][w2b DZ]
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) {
+      const int q = threadIdx.x + k * kThreads;
+      if (q >= fsz) break;
+      TN s = 0;
+      if (q < K * DZ) {
+        const int a = q / DZ, b = q % DZ;
+        for (int row = 0; row < rows; ++row) s += E[row * LDK + a] * CU[row * LDZ + b];
+      } else if (q < K * DZ + DZ) {
+        const int b = q - K * DZ;
+        for (int row = 0; row < rows; ++row) s += CU[row * LDZ + b];
+      } else if (q < K * DZ + DZ + DZ * DZ) {
+        const int a = (q - K * DZ - DZ) / DZ, b = (q - K * DZ - DZ) % DZ;
+        for (int row = 0; row < rows; ++row) s += ssp(U[row * LDZ + a]) * CW[row * LDZ + b];
+      } else {
+        const int b = q - K * DZ - DZ - DZ * DZ;
+        for (int row = 0; row < rows; ++row) s += CW[row * LDZ + b];
+      }
+      acc[k] += s;
+    }
+  }
+  TN* out = fslot + ((size_t)blockIdx.x * L * 3 + blockIdx.y) * fsz;
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) {
+    const int q = threadIdx.x + k * kThreads;
+    if (q < fsz) out[q] = acc[k];
+  }
+}
+
+template <typename TN>
+__global__ __launch_bounds__(kThreads) void k_bwd_reduce(Dims d, ParamLayout pl, int64_t n_params, int n_net,
+                                                         const TN* __restrict__ gslot, int n_filt,
+                                                         const TN* __restrict__ fslot, double* __restrict__ grad) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_params) return;
+  const int fsz = d.K * d.DZ + d.DZ + d.DZ * d.DZ + d.DZ;
+  // is q inside a filter block?
+  for (int n = 0; n < d.L; ++n) {
+    const int64_t f0 = pl.layer[n].w1W[0];
+    if (q >= f0 && q < f0 + 3 * fsz) {
+      const int seg = n * 3 + (int)((q - f0) / fsz), o = (int)((q - f0) % fsz);
+      double s = 0.0;
+      for (int b = 0; b < n_filt; ++b) s += (double)fslot[((size_t)b * d.L * 3 + seg) * fsz + o];
+      grad[q] += s;
+      return;
+    }
+  }
+  double s = 0.0;
+  for (int b = 0; b < n_net; ++b) s += (double)gslot[(size_t)b * n_params + q];
+  grad[q] += s;
+}
+
+}  // namespace
+
+// walkers per group of k_bwd_net, chosen from the LDS budget
+template <typename TN>
+static size_t bwd_net_lds(const Dims& d, int WB) {
+  const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDM = ld_pad<TN>((d.M + 15) & ~15);
+  const size_t RW = (size_t)WB * d.N;
+  const size_t heads = 3 * RW * LDX + RW * LDM + 6 * (size_t)WB * LDX;  // kappa buffers, then the eta ones
+  const size_t layers = 4 * RW * LDZ;
+  return (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
+         ((size_t)((WB + 3) & ~3) + 2 * RW * LDX + std::max(heads, layers)) * sizeof(TN);
+}
+
+template <typename TN>
+static int bwd_wb(const Dims& d) {
+  int wb = std::max(1, 64 / d.N);
+  while (wb > 1 && bwd_net_lds<TN>(d, wb) > 80 * 1024) --wb;
+  return wb;
+}
+
+static size_t filt_fsz(const Dims& d) { return (size_t)d.K * d.DZ + d.DZ + (size_t)d.DZ * d.DZ + d.DZ; }
+
 size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32) {
-  (void)c;
-  (void)tile;
-  (void)fp32;
-  return 0;
+  const Dims& d = c->d;
+  const size_t tn = fp32 ? sizeof(float) : sizeof(double);
+  size_t b = 0;
+  b += (size_t)kSlotsNet * c->pl.total * tn;                       // net slots
+  b += (size_t)kSlotsFilter * d.L * 3 * filt_fsz(d) * tn;          // filter slots
+  b += (size_t)tile * d.L * d.n_pairs * d.DZ * tn;                 // filter cotangents
+  return b + 1024;
 }
-void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
-                     bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params) {
-  (void)c; (void)s; (void)nw; (void)r; (void)P; (void)fp32; (void)bf16; (void)ct; (void)ws; (void)L;
-  (void)grad_params;
+
+bool backward_supported(const pn_ctx* c, bool fp32) {
+  const Dims& d = c->d;
+  if (filt_fsz(d) > (size_t)32 * kThreads) return false;
+  size_t lds = fp32 ? bwd_net_lds<float>(d, bwd_wb<float>(d)) : bwd_net_lds<double>(d, bwd_wb<double>(d));
+  return lds <= 160 * 1024;
 }
+
+template <typename TN>
+static void run_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, const double* ct,
+                         char* ws, const WsLayout& L, double* grad) {
+  const Dims& d = c->d;
+  const int64_t np = c->pl.total;
+  TN* gslot = reinterpret_cast<TN*>(ws + L.gpart);
+  TN* fslot = gslot + (size_t)kSlotsNet * np;
+  TN* ctw = fslot + (size_t)kSlotsFilter * d.L * 3 * filt_fsz(d);
+  const int WB = bwd_wb<TN>(d);
+  const size_t lds = bwd_net_lds<TN>(d, WB);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bwd_net<TN>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  const int64_t ng = (nw + WB - 1) / WB;
+  const int nb_net = (int)std::min<int64_t>(ng, kSlotsNet);
+  hipLaunchKernelGGL(k_bwd_net<TN>, dim3(nb_net), dim3(kThreads), lds, s, d, c->t, nw, WB, P, c->pl,
+                     reinterpret_cast<const TN*>(ws + L.xval), reinterpret_cast<const TN*>(ws + L.hval),
+                     reinterpret_cast<const TN*>(ws + L.filt), reinterpret_cast<const double*>(ws + L.phi),
+                     reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet), ct,
+                     ctw, gslot, np);
+  const int n_same = d.n_up * (d.n_up - 1) / 2 + d.n_dn * (d.n_dn - 1) / 2;
+  const int64_t max_np = std::max<int64_t>(std::max(n_same, d.n_ee - n_same), (int64_t)d.N * d.NN);
+  const int nb_f = (int)std::min<int64_t>((nw * max_np + kFiltRows - 1) / kFiltRows, kSlotsFilter);
+  const size_t lds_f = kFiltRows * sizeof(double) +
+                       (size_t)kFiltRows * (ld_pad<TN>(d.K) + 3 * ld_pad<TN>(d.DZ)) * sizeof(TN);
+  hipLaunchKernelGGL(k_bwd_filter<TN>, dim3(nb_f, d.L * 3), dim3(kThreads), lds_f, s, d, c->t, nw, r, P, c->pl, ctw,
+                     fslot, n_same);
+  hipLaunchKernelGGL(k_bwd_reduce<TN>, dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d,
+                     c->pl, np, nb_net, gslot, nb_f, fslot, grad);
+}
+
+void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32, bool bf16,
+                     const double* ct, char* ws, const WsLayout& L, double* grad_params) {
+  (void)bf16;
+  if (fp32)
+    run_backward<float>(c, s, nw, r, static_cast<const float*>(P), ct, ws, L, grad_params);
+  else
+    run_backward<double>(c, s, nw, r, static_cast<const double*>(P), ct, ws, L, grad_params);
+}
+
 }  // namespace pn

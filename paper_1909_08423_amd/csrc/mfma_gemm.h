@@ -103,7 +103,7 @@ struct MfmaChain<float, KQ> {
   }
 };
 
-template <typename TN, int KQ>
+template <typename TN, int KQ, bool WT = false>
 __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int ldw, int O,
                                             int ncol, TN* Y, int ldy, bool accumulate, bool bf16) {
   typedef typename MfmaTile<TN>::acc_t acc_t;
@@ -127,7 +127,8 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
     const bool colok = col < ncol;
     TN bfrag[KQ];
 #pragma unroll
-    for (int s = 0; s < KQ; ++s) bfrag[s] = colok ? W[(size_t)(g * KQ + s) * ldw + col] : TN(0);
+    for (int s = 0; s < KQ; ++s)
+      bfrag[s] = colok ? (WT ? W[(size_t)col * ldw + g * KQ + s] : W[(size_t)(g * KQ + s) * ldw + col]) : TN(0);
     for (int rt = rt0; rt < n_rt; rt += rt_step) {
       const int r = min((rt << 4) + c16, rows - 1);
       const TN* xr = X + (size_t)r * ldx + g * KQ;
@@ -183,6 +184,22 @@ __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I,
     default:
       gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
       gemm_mfma_k<TN, 16>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      break;
+  }
+}
+
+// Y[rows][O] (+)= X[rows][I] * W^T with W stored [O][I] row-major (the
+// transposed products of the adjoint pass).  I in {16, 32, 64, 128}.
+template <typename TN>
+__device__ __forceinline__ void gemm_mfma_wt(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W, int O,
+                                             TN* Y, int ldy, bool accumulate) {
+  switch (I) {
+    case 16: gemm_mfma_k<TN, 4, true>(X, ldx, rows, W, I, O, O, Y, ldy, accumulate, false); break;
+    case 32: gemm_mfma_k<TN, 8, true>(X, ldx, rows, W, I, O, O, Y, ldy, accumulate, false); break;
+    case 64: gemm_mfma_k<TN, 16, true>(X, ldx, rows, W, I, O, O, Y, ldy, accumulate, false); break;
+    default:
+      gemm_mfma_k<TN, 16, true>(X, ldx, rows, W, I, O, O, Y, ldy, accumulate, false);
+      gemm_mfma_k<TN, 16, true>(X + 64, ldx, rows, W + 64, I, O, O, Y, ldy, true, false);
       break;
   }
 }

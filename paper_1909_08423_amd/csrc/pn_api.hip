@@ -22,13 +22,13 @@ bool tangent_chunk_supported(int T);
 void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
                      bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params);
 size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32);
+bool backward_supported(const pn_ctx* c, bool fp32);
 
 namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kWsBudget = size_t(6) << 30;  // walker tiles keep the workspace below ~6 GiB
 constexpr size_t kLdsMax = 160 * 1024;
-constexpr bool kBackwardReady = false;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -193,7 +193,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   L.jtan = region((size_t)tile * L.n_chunks * Tp * 8);
   L.partial = region((size_t)tile * L.n_chunks * 2 * 8);
   // grad scratch for calls that want lap/eloc without grad
-  L.adj = region((size_t)tile * N * 3 * 8);
+  L.adj = region((size_t)tile * std::max(N * 3, 2) * 8);
   L.xval = 0;
   L.gpart = 0;
   if (backward) {
@@ -562,8 +562,8 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
   if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
   if (nw == 0) return PN_OK;
   if (!r || !params || !ct_logabs || !grad_params || !ws) return PN_ERR_INVALID_ARG;
-  if (!kBackwardReady) return PN_ERR_UNSUPPORTED_SHAPE;
   const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
+  if (!backward_supported(c, !fp64)) return PN_ERR_UNSUPPORTED_SHAPE;
   WsLayout L = plan(c, nw, prec, true);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
   char* base = static_cast<char*>(ws);
@@ -572,7 +572,25 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
     launch_convert_params(s, c->pl.total, params, reinterpret_cast<float*>(base + L.params_net));
     P = base + L.params_net;
   }
-  launch_backward(c, s, nw, r, P, !fp64, bf16, ct_logabs, base, L, grad_params);
+  const Dims& d = c->d;
+  // the value pass is recomputed here (nothing is kept between calls); its
+  // ln|psi| and sign go to scratch
+  double* la = reinterpret_cast<double*>(base + L.adj);
+  double* sg = la + L.tile;
+  for (int64_t w0 = 0; w0 < nw; w0 += L.tile) {
+    const int64_t n = std::min<int64_t>(L.tile, nw - w0);
+    const double* rt = r + w0 * d.N * 3;
+    launch_geometry_orbitals(c, s, n, rt, base, L);
+    if (fp64) {
+      launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
+      launch_net_value<double>(c, s, n, static_cast<const double*>(P), base, L, false);
+    } else {
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+    }
+    launch_slater_value(c, s, n, base, L, la, sg);
+    launch_backward(c, s, n, rt, P, !fp64, bf16, ct_logabs + w0, base, L, grad_params);
+  }
   if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
   return PN_OK;
 }

@@ -60,9 +60,13 @@ def run(idx):
     rng = np.random.default_rng(77 + idx)
     sample = np.sort(rng.choice(full.walkers.shape[0], n_sample, replace=False))
     out_s = o.evaluate(full.walkers[sample])
+    # parameter gradient of sum_w ct_w ln|psi_w| on a few walkers (value-path adjoint)
+    nb = min(6, walkers.shape[0])
+    ct = np.random.default_rng(500 + idx).standard_normal(nb)
+    bwd = o.param_grad_logabs(walkers[:nb], ct).numpy()
     path = os.path.join(HERE, f"oracle_cfg{idx}.npz")
     np.savez_compressed(
-        path, walkers=walkers,
+        path, walkers=walkers, bwd_ct=ct, bwd_grad=bwd,
         logabs=out["logabs"].numpy(), sign=out["sign"].numpy(), grad=out["grad"].numpy(),
         lap=out["lap"].numpy(), eloc=out["eloc"].numpy(),
         full_sample=sample, full_logabs=out_s["logabs"].numpy(), full_sign=out_s["sign"].numpy(),

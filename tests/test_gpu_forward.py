@@ -120,3 +120,85 @@ def test_mixed_precision_error_statement(pn, idx, prec, bound):
     print(f"[{prec} cfg{idx}] p50/p99/max: {summ}")
     np.testing.assert_array_equal(out["sign"], fx["sign"])
     assert summ["eloc"][1] < bound and summ["logabs"][1] < bound
+
+
+# ------------------------------------------------------------- backward ----
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_backward_fp64_matches_oracle(pn, idx):
+    """Value-path adjoint grad += sum_w ct_w d ln|psi_w| / d theta (the
+    gradient the Hermitian estimator of Methods eq. "trainig" needs) against
+    the oracle's autograd gradient.  FP64 bar: ||d g|| <= 1e-8 ||g|| and
+    every component within 1e-7 max|g|."""
+    fx = load_fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    ct = fx["bwd_ct"]
+    nb = ct.shape[0]
+    announce(f"fp64 backward workload {idx} B={nb}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(fx["walkers"][:nb], dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    g0 = torch.full((ctx.param_count,), 0.5, dtype=torch.float64, device="cuda")
+    g = ctx.eval_backward(r, th, torch.tensor(ct, device="cuda"), pn.PN_PREC_FP64, grad_params=g0.clone())
+    torch.cuda.synchronize()
+    got = g.cpu().numpy() - 0.5  # the call accumulates
+    ref = fx["bwd_grad"]
+    assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.max(np.abs(got - ref)) <= 1e-7 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("idx,prec", [(2, "fp32"), (3, "fp32"), (3, "bf16")])
+def test_backward_mixed_error_statement(pn, idx, prec):
+    fx = load_fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    ct = fx["bwd_ct"]
+    nb = ct.shape[0]
+    announce(f"{prec} backward workload {idx}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(fx["walkers"][:nb], dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    g = ctx.eval_backward(r, th, torch.tensor(ct, device="cuda"), pn._lib.PRECISIONS[prec])
+    torch.cuda.synchronize()
+    got, ref = g.cpu().numpy(), fx["bwd_grad"]
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"[{prec} backward cfg{idx}] relative L2 error {rel:.3e}")
+    assert rel < (1e-3 if prec == "fp32" else 0.2)
+
+
+def test_backward_deterministic_and_batch_split(pn):
+    """Two identical calls give identical bits; two half batches accumulated
+    into one buffer equal the full batch to rounding."""
+    w = make_config(2, n_walkers=600)
+    announce("backward determinism, workload 2, B=600")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ct = torch.tensor(np.random.default_rng(3).standard_normal(600), device="cuda")
+    a = ctx.eval_backward(r, th, ct, pn.PN_PREC_FP64)
+    b = ctx.eval_backward(r, th, ct, pn.PN_PREC_FP64)
+    c = torch.zeros_like(a)
+    ctx.eval_backward(r[:300].contiguous(), th, ct[:300].contiguous(), pn.PN_PREC_FP64, grad_params=c)
+    ctx.eval_backward(r[300:].contiguous(), th, ct[300:].contiguous(), pn.PN_PREC_FP64, grad_params=c)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert float(torch.linalg.norm(a - c)) <= 1e-12 * float(torch.linalg.norm(a))
+
+
+def test_backward_against_finite_differences(pn):
+    """Central differences of sum_w ct_w ln|psi_w| computed by the GPU value
+    path, for 24 random parameters of the H10 workload (FP64)."""
+    w = make_config(3, n_walkers=32)
+    announce("backward vs finite differences, workload 3")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ct = torch.tensor(np.random.default_rng(9).standard_normal(32), device="cuda")
+    g = ctx.eval_backward(r, th, ct, pn.PN_PREC_FP64).cpu().numpy()
+    idx = np.random.default_rng(10).choice(th.numel(), 24, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = torch.zeros_like(th)
+        e[int(k)] = h
+        fp = float((ct * ctx.eval(r, th + e, pn.PN_PREC_FP64, want_derivs=False)["logabs"]).sum())
+        fm = float((ct * ctx.eval(r, th - e, pn.PN_PREC_FP64, want_derivs=False)["logabs"]).sum())
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (int(k), fd, g[k])
