@@ -152,6 +152,55 @@ pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walk
                            const double* ct_logabs, double* grad_params, void* ws,
                            size_t ws_bytes);
 
+/* ---- one VMC step of a job (serving) -------------------------------------
+ * Methods, "Ansatz optimization": the walkers sample |psi|^2 by Metropolis
+ * moves, the loss is the mean clipped local energy, its gradient comes from
+ * the Hermitian estimator (eq. "trainig") and the parameters follow AdamW
+ * with the decaying learning rate lr0 / (1 + t / t0) (Table 2).
+ *
+ * pn_vmc_step enqueues, on `stream`, for one job:
+ *   1. ln|psi| at r (current parameters);
+ *   2. all-electron Gaussian proposal r' = r + sigma xi, xi from the
+ *      counter-based Philox4x32-10 generator keyed by `seed` with counter
+ *      (walker, step, call, 0) (two Box-Muller normals per call, call =
+ *      0, 1, ...; the acceptance uniform uses call 0xFFFFFFFF);
+ *   3. ln|psi| at r' and acceptance when u < exp(2 (ln|psi'| - ln|psi|));
+ *   4. E_loc at the new r;
+ *   5. clipping: median m and mean absolute deviation delta of E_loc,
+ *      window w = clip_q * delta, E~ = E inside the window, else
+ *      m + sgn(E - m) w (1 + ln(|E - m| / w)); L = mean E~;
+ *   6. g = (2 / B) sum_w (E~_w - L) d ln|psi_w| / d theta;
+ *   7. AdamW on the FP64 parameters with step t = `step`.
+ * A step whose E_loc has a non-finite value skips 6 and 7 (stats[5] = 0).
+ * All buffers are the caller's; the call does not synchronise.  Results are
+ * deterministic and independent of other work on the device.
+ * Limits: n_walkers <= 16384 (the clipping statistics run in one block). */
+typedef struct {
+  double sigma;        /* Metropolis step, bohr (0.3)                      */
+  double lr0, t0;      /* learning rate lr0 / (1 + t / t0) (0.01, 200)    */
+  double clip_q;       /* clipping window in mean deviations (5)          */
+  double beta1, beta2, eps, weight_decay; /* AdamW (0.9, 0.999, 1e-8, 0.01) */
+} pn_vmc_hparams;
+
+typedef struct {
+  int64_t n_walkers;
+  double* r;           /* [B][n_elec][3] walker positions, updated        */
+  double* params;      /* [n_params] FP64 parameters, updated             */
+  double* adam_m;      /* [n_params] first moment, updated (start at 0)   */
+  double* adam_v;      /* [n_params] second moment, updated (start at 0)  */
+  double* eloc;        /* [B] out: E_loc at the new positions             */
+  double* stats;       /* [8] out: mean E_loc, std E_loc, acceptance,
+                          clipped mean L, non-finite count, step applied
+                          (1/0), median, clipping window                  */
+  uint64_t seed;
+  int64_t step;        /* t: RNG counter and AdamW step (0 for the first) */
+} pn_vmc_job;
+
+/* Workspace bytes for pn_vmc_step with n_walkers walkers. */
+pn_status pn_vmc_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+pn_status pn_vmc_step(const pn_ctx* ctx, hipStream_t stream, const pn_vmc_job* job, pn_precision prec,
+                      const pn_vmc_hparams* hp, void* ws, size_t ws_bytes);
+
 /* Per-stage kernel timing, for profiling.  When enabled, pn_eval records
  * a HIP event before and after each of its stages on the call's stream.
  * pn_stage_times waits for the recorded events and returns, per stage, the

@@ -14,4 +14,6 @@ from ._lib import (  # noqa: F401
     PauliNetError,
     library_path,
     load_library,
+    vmc_step,
+    vmc_workspace_bytes,
 )

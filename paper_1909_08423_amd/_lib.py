@@ -55,6 +55,29 @@ class pn_net_desc(ctypes.Structure):
     ]
 
 
+class pn_vmc_hparams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("sigma", "lr0", "t0", "clip_q", "beta1", "beta2", "eps", "weight_decay")]
+
+
+class pn_vmc_job(ctypes.Structure):
+    _fields_ = [
+        ("n_walkers", ctypes.c_int64),
+        ("r", ctypes.c_void_p),
+        ("params", ctypes.c_void_p),
+        ("adam_m", ctypes.c_void_p),
+        ("adam_v", ctypes.c_void_p),
+        ("eloc", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64),
+        ("step", ctypes.c_int64),
+    ]
+
+
+DEFAULT_HPARAMS = dict(sigma=0.3, lr0=0.01, t0=200.0, clip_q=5.0, beta1=0.9, beta2=0.999, eps=1e-8,
+                       weight_decay=0.01)
+
+
 class PauliNetError(RuntimeError):
     pass
 
@@ -93,6 +116,11 @@ def load_library():
     lib.pn_stage_timing.restype = i32
     lib.pn_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.pn_stage_times.restype = i32
+    lib.pn_vmc_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_vmc_workspace_bytes.restype = i32
+    lib.pn_vmc_step.argtypes = [vp, vp, ctypes.POINTER(pn_vmc_job), i32, ctypes.POINTER(pn_vmc_hparams), vp,
+                                ctypes.c_size_t]
+    lib.pn_vmc_step.restype = i32
     lib.pn_status_string.argtypes = [i32]
     lib.pn_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -246,3 +274,33 @@ class PauliNetContext:
                                         _ptr(ct_logabs), _ptr(grad_params), _ptr(ws), ws.numel())
         _check(st, "pn_eval_backward")
         return grad_params
+
+
+def vmc_workspace_bytes(ctx, n_walkers, prec):
+    b = ctypes.c_size_t()
+    _check(ctx._lib.pn_vmc_workspace_bytes(ctx._ctx, int(n_walkers), int(prec), ctypes.byref(b)),
+           "pn_vmc_workspace_bytes")
+    return int(b.value)
+
+
+def vmc_step(ctx, state, prec, hparams=None, stream=None):
+    """One VMC step of a job on `stream` (torch stream; default current).
+    `state` holds device tensors r, params, adam_m, adam_v, eloc, stats, ws
+    and ints seed, step; the tensors are updated in place."""
+    import torch
+    hp = dict(DEFAULT_HPARAMS)
+    hp.update(hparams or {})
+    h = pn_vmc_hparams(**hp)
+    j = pn_vmc_job()
+    j.n_walkers = int(state["r"].shape[0])
+    for k in ("r", "params", "adam_m", "adam_v", "eloc", "stats"):
+        t = state[k]
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise PauliNetError(f"{k} must be a contiguous float64 device tensor")
+        setattr(j, k, t.data_ptr())
+    j.seed = int(state["seed"]) & 0xFFFFFFFFFFFFFFFF
+    j.step = int(state["step"])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ws = state["ws"]
+    _check(ctx._lib.pn_vmc_step(ctx._ctx, ctypes.c_void_p(st.cuda_stream), ctypes.byref(j), int(prec),
+                                ctypes.byref(h), ctypes.c_void_p(ws.data_ptr()), ws.numel()), "pn_vmc_step")
