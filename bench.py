@@ -106,6 +106,54 @@ def cpu_baseline(workload_idx, budget_s=15.0, chunk=8):
             "sample": f"first {n} walkers of the same workload, {chunk} per call, {dt:.1f} s"}
 
 
+def time_vmc_step(pn, ctx, w, prec, steps, warmup, torch):
+    """Full VMC step of one job (Metropolis + E_loc + clipping + gradient +
+    AdamW) on the benchmark batch."""
+    st = {
+        "r": torch.tensor(w.walkers, dtype=torch.float64, device="cuda"),
+        "params": torch.tensor(w.params, dtype=torch.float64, device="cuda"),
+        "adam_m": torch.zeros(w.params.shape[0], dtype=torch.float64, device="cuda"),
+        "adam_v": torch.zeros(w.params.shape[0], dtype=torch.float64, device="cuda"),
+        "eloc": torch.empty(w.walkers.shape[0], dtype=torch.float64, device="cuda"),
+        "stats": torch.zeros(8, dtype=torch.float64, device="cuda"),
+        "ws": torch.empty(pn.vmc_workspace_bytes(ctx, w.walkers.shape[0], prec), dtype=torch.uint8, device="cuda"),
+        "seed": 1234, "step": 0,
+    }
+    for _ in range(warmup):
+        pn.vmc_step(ctx, st, prec)
+        st["step"] += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pn.vmc_step(ctx, st, prec)
+        st["step"] += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"walker_steps_per_s": w.walkers.shape[0] * steps / dt, "ms_per_step": dt / steps * 1e3,
+            "steps": steps, "last_stats": st["stats"].cpu().numpy().tolist()}
+
+
+def run_serving(pn, prec, n_jobs, n_steps, torch):
+    """The serving stream (H-chains and atoms, 2-18 electrons, 1-32
+    determinants, 1024-8192 walkers, Poisson arrivals), shortened to n_jobs
+    jobs of n_steps steps."""
+    from paper_1909_08423_amd.serve import GpuBackend, JobSpec, Server, summarize
+    from synth import make_serving_jobs
+    jobs = make_serving_jobs(n_jobs=n_jobs, n_steps=n_steps, mean_gap_s=0.05)
+    specs = [JobSpec(j.job_id, j.arrival_s, j.n_steps, j.workload.system, j.workload.net, j.workload.params,
+                     j.workload.walkers, seed=1000 + j.job_id) for j in jobs]
+    be = GpuBackend(prec=prec, n_streams=8)
+    srv = Server(be, mem_budget_bytes=64 << 30, max_active=16)
+    t0 = time.perf_counter()
+    recs = srv.run(specs)
+    torch.cuda.synchronize()
+    out = summarize(recs, time.perf_counter() - t0)
+    out.update({"jobs": n_jobs, "steps_per_job": n_steps, "max_concurrency": srv.max_concurrency,
+                "mem_budget_GiB": 64, "electrons": [int(s.walkers.shape[1]) for s in specs],
+                "walkers": [int(s.walkers.shape[0]) for s in specs]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +163,9 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=12)
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the walker batch shards "
@@ -194,6 +245,9 @@ def main():
         "stages_ms_per_step_fp64": {k: v[0] / max(v[1], 1) for k, v in st_64.items() if v[1] > 0},
         "roofline": roof,
     }
+    res["vmc_step"] = time_vmc_step(pn, ctx, w, P[args.prec], max(3, args.steps // 4), 1, torch)
+    if not args.no_serve:
+        res["serving"] = run_serving(pn, P[args.prec], args.serve_jobs, args.serve_steps, torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(res), flush=True)
