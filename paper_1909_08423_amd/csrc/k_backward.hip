@@ -58,6 +58,40 @@ __device__ void outer_acc_ssp(const TN* U, int ldu, int A, const TN* Y, int ldy,
     slot[q] = first ? s : slot[q] + s;
   }
 }
+// slot[a*B + b] (+)= sum_r f(X[r][a]) Y[r][b] on the matrix cores (f = identity
+// or ssp); A and B multiples of 16.  Rows are reduced in chunks of 32: lane
+// group g takes rows g*8 .. g*8+7 of a chunk, rows past `rows` read as zero.
+template <typename TN, bool SSP>
+__device__ void outer_mfma(const TN* X, int ldx, int A, const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
+  typedef typename MfmaTile<TN>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int nbt = B / 16, nt = (A / 16) * nbt;
+  for (int tt = wv; tt < nt; tt += nwv) {
+    const int a0 = (tt / nbt) * 16, b0 = (tt % nbt) * 16;
+    acc_t c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[v] = 0;
+    for (int r0 = 0; r0 < rows; r0 += 32) {
+      TN af[8], bf[8];
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        const int r = r0 + g * 8 + s2;
+        const bool ok = r < rows;
+        const TN xv = ok ? X[(size_t)r * ldx + a0 + c16] : TN(0);
+        af[s2] = SSP ? (ok ? ssp(xv) : TN(0)) : xv;
+        bf[s2] = ok ? Y[(size_t)r * ldy + b0 + c16] : TN(0);
+      }
+      c = MfmaChain<TN, 8>::run(af, bf, c, false);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const size_t q = (size_t)(a0 + MfmaTile<TN>::row_of(lane, v)) * B + b0 + c16;
+      slot[q] = first ? c[v] : slot[q] + c[v];
+    }
+  }
+}
+
 // slot[b] (+)= sum_r Y[r][b]
 template <typename TN>
 __device__ void colsum_acc(const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
@@ -170,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         for (int r = 0; r < nwb; ++r) s += cw[r];
         slot[pl.eb3] = first ? s : slot[pl.eb3] + s;
       }
-      outer_acc_ssp<TN>(U1, LDX, DX, C2, LDX, DX, nwb, slot + pl.eW2, first);
+      outer_mfma<TN, true>(U1, LDX, DX, C2, LDX, DX, nwb, slot + pl.eW2, first);
       colsum_acc<TN>(C2, LDX, DX, nwb, slot + pl.eb2, first);
       gemm_mfma_wt<TN>(C2, LDX, nwb, DX, P + pl.eW2, DX, C1, LDX, false);
       __syncthreads();
@@ -179,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         C1[r * LDX + x] *= sig(U1[r * LDX + x]);
       }
       __syncthreads();
-      outer_acc<TN>(Sv, LDX, DX, C1, LDX, DX, nwb, slot + pl.eW1, first);
+      outer_mfma<TN, false>(Sv, LDX, DX, C1, LDX, DX, nwb, slot + pl.eW1, first);
       colsum_acc<TN>(C1, LDX, DX, nwb, slot + pl.eb1, first);
       gemm_mfma_wt<TN>(C1, LDX, nwb, DX, P + pl.eW1, DX, C2, LDX, false);  // d/d s
       __syncthreads();
@@ -212,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
       B[r * LDX + x] = s * sig(Cb[r * LDX + x]);  // d/d u2
     }
     __syncthreads();
-    outer_acc_ssp<TN>(A, LDX, DX, B, LDX, DX, R, slot + pl.kW2, first);
+    outer_mfma<TN, true>(A, LDX, DX, B, LDX, DX, R, slot + pl.kW2, first);
     colsum_acc<TN>(B, LDX, DX, R, slot + pl.kb2, first);
     gemm_mfma_wt<TN>(B, LDX, R, DX, P + pl.kW2, DX, Cb, LDX, false);
     __syncthreads();
@@ -221,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
       Cb[r * LDX + x] *= sig(A[r * LDX + x]);  // d/d u1
     }
     __syncthreads();
-    outer_acc<TN>(X, LDX, DX, Cb, LDX, DX, R, slot + pl.kW1, first);
+    outer_mfma<TN, false>(X, LDX, DX, Cb, LDX, DX, R, slot + pl.kW1, first);
     colsum_acc<TN>(Cb, LDX, DX, R, slot + pl.kb1, first);
     gemm_mfma_wt<TN>(Cb, LDX, R, DX, P + pl.kW1, DX, CX, LDX, true);
     __syncthreads();
@@ -253,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
           Z[row * LDZ + z] = acc;
         }
         __syncthreads();
-        outer_acc<TN>(Z, LDZ, DZ, CX, LDX, DX, R, slot + Lp.gW[ch], first);
+        outer_mfma<TN, false>(Z, LDZ, DZ, CX, LDX, DX, R, slot + Lp.gW[ch], first);
         colsum_acc<TN>(CX, LDX, DX, R, slot + Lp.gb[ch], first);
         gemm_mfma_wt<TN>(CX, LDX, R, DX, P + Lp.gW[ch], DZ, CZ, LDZ, false);  // d/d z
         __syncthreads();
@@ -305,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         __syncthreads();
       }
       // h = x W_h + b_h
-      outer_acc<TN>(X, LDX, DX, CH, LDZ, DZ, R, slot + Lp.hW, first);
+      outer_mfma<TN, false>(X, LDX, DX, CH, LDZ, DZ, R, slot + Lp.hW, first);
       colsum_acc<TN>(CH, LDZ, DZ, R, slot + Lp.hb, first);
       gemm_mfma_wt<TN>(CH, LDZ, R, DZ, P + Lp.hW, DX, CX, LDX, true);
       __syncthreads();
@@ -336,19 +370,27 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
   TN* CU = CW + PT * LDZ;                        // [PT][LDZ] d/d u
   const ParamLayout::Layer& Lp = pl.layer[layer];
   const int fsz = K * DZ + DZ + DZ * DZ + DZ;
-  // gradient accumulators owned by this thread: indices q = tid + k * blockDim
-  constexpr int kAcc = 32;  // fsz <= kAcc * kThreads  (K, DZ <= 64 -> fsz <= 8320)
-  TN acc[kAcc];
+  // weight gradients dW1 = E^T CU and dW2 = ssp(U)^T CW on the matrix cores:
+  // every wavefront keeps its 16 x 16 output tiles in registers across all
+  // row tiles; the reduction runs over the kFiltRows = 32 rows of a tile.
+  typedef typename MfmaTile<TN>::acc_t acc_t;
+  constexpr int kMaxT = 8;  // tiles per wavefront: (K/16 + DZ/16) * DZ/16 <= 32
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+  const int nz = DZ / 16, nt1 = (K / 16) * nz, nt = nt1 + nz * nz;
+  acc_t accs[kMaxT];
 #pragma unroll
-  for (int k = 0; k < kAcc; ++k) acc[k] = 0;
+  for (int k = 0; k < kMaxT; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accs[k][v] = 0;
+  TN bacc1 = 0, bacc2 = 0;  // thread z < DZ owns db1[z], db2[z]
   for (int64_t row0 = (int64_t)blockIdx.x * PT; row0 < nrows; row0 += (int64_t)gridDim.x * PT) {
     const int rows = (int)min((int64_t)PT, nrows - row0);
     __syncthreads();
     for (int q = threadIdx.x; q < PT; q += blockDim.x) {
       double v = 1.0;
       if (q < rows) {
-        const int64_t g = row0 + q, w = g / np;
-        const int p = p_lo + (int)(g % np);
+        const int64_t gq = row0 + q, w = gq / np;
+        const int p = p_lo + (int)(gq % np);
         const double* rw = r + w * d.N * 3;
         double x, y, z;
         if (p < d.n_ee) {
@@ -380,8 +422,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
       const int row = q / DZ, z = q % DZ;
       TN v = 0;
       if (row < rows) {
-        const int64_t g = row0 + row, w = g / np;
-        const int p = p_lo + (int)(g % np);
+        const int64_t gq = row0 + row, w = gq / np;
+        const int p = p_lo + (int)(gq % np);
         v = ctw[((w * L + layer) * d.n_pairs + p) * DZ + z];
       }
       CW[row * LDZ + z] = v;
@@ -395,36 +437,64 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
     __syncthreads();
     for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) {
       const int row = q / DZ, z = q % DZ;
-      CU[row * LDZ + z] = row < rows ? CU[row * LDZ + z] * sig(U[row * LDZ + z]) : TN(0);
+      const TN u = U[row * LDZ + z];
+      CU[row * LDZ + z] = row < rows ? CU[row * LDZ + z] * sig(u) : TN(0);
+      U[row * LDZ + z] = row < rows ? ssp(u) : TN(0);  // hidden activation (zero on padding rows)
     }
     __syncthreads();
-    // accumulate: [w1W K x DZ][w1b DZ][w2W DZ x DZ][w2b DZ]
 #pragma unroll
-    for (int k = 0; k < kAcc; ++k) {
-      const int q = threadIdx.x + k * kThreads;
-      if (q >= fsz) break;
-      TN s = 0;
-      if (q < K * DZ) {
-        const int a = q / DZ, b = q % DZ;
-        for (int row = 0; row < rows; ++row) s += E[row * LDK + a] * CU[row * LDZ + b];
-      } else if (q < K * DZ + DZ) {
-        const int b = q - K * DZ;
-        for (int row = 0; row < rows; ++row) s += CU[row * LDZ + b];
-      } else if (q < K * DZ + DZ + DZ * DZ) {
-        const int a = (q - K * DZ - DZ) / DZ, b = (q - K * DZ - DZ) % DZ;
-        for (int row = 0; row < rows; ++row) s += ssp(U[row * LDZ + a]) * CW[row * LDZ + b];
-      } else {
-        const int b = q - K * DZ - DZ - DZ * DZ;
-        for (int row = 0; row < rows; ++row) s += CW[row * LDZ + b];
+    for (int k = 0; k < kMaxT; ++k) {
+      const int tt = wv + k * (kThreads / 64);
+      if (tt < nt) {
+        const TN* X;
+        const TN* Y;
+        int ldx2, a0, b0;
+        if (tt < nt1) {
+          X = E;
+          ldx2 = LDK;
+          Y = CU;
+          a0 = (tt / nz) * 16;
+          b0 = (tt % nz) * 16;
+        } else {
+          X = U;
+          ldx2 = LDZ;
+          Y = CW;
+          a0 = ((tt - nt1) / nz) * 16;
+          b0 = ((tt - nt1) % nz) * 16;
+        }
+        TN af[8], bf[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+          af[s2] = X[(g * 8 + s2) * ldx2 + a0 + c16];
+          bf[s2] = Y[(g * 8 + s2) * LDZ + b0 + c16];
+        }
+        accs[k] = MfmaChain<TN, 8>::run(af, bf, accs[k], false);
       }
-      acc[k] += s;
+    }
+    if (threadIdx.x < DZ) {
+      for (int row = 0; row < rows; ++row) {
+        bacc1 += CU[row * LDZ + threadIdx.x];
+        bacc2 += CW[row * LDZ + threadIdx.x];
+      }
     }
   }
   TN* out = fslot + ((size_t)blockIdx.x * L * 3 + blockIdx.y) * fsz;
+  // layout of a filter block: [w1W K x DZ][w1b DZ][w2W DZ x DZ][w2b DZ]
 #pragma unroll
-  for (int k = 0; k < kAcc; ++k) {
-    const int q = threadIdx.x + k * kThreads;
-    if (q < fsz) out[q] = acc[k];
+  for (int k = 0; k < kMaxT; ++k) {
+    const int tt = wv + k * (kThreads / 64);
+    if (tt < nt) {
+      const bool first_mat = tt < nt1;
+      const int a0 = first_mat ? (tt / nz) * 16 : ((tt - nt1) / nz) * 16;
+      const int b0 = first_mat ? (tt % nz) * 16 : ((tt - nt1) % nz) * 16;
+      const int base = first_mat ? 0 : K * DZ + DZ;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[base + (a0 + MfmaTile<TN>::row_of(lane, v)) * DZ + b0 + c16] = accs[k][v];
+    }
+  }
+  if (threadIdx.x < DZ) {
+    out[K * DZ + threadIdx.x] = bacc1;
+    out[K * DZ + DZ + DZ * DZ + threadIdx.x] = bacc2;
   }
 }
 
@@ -485,7 +555,7 @@ size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32) {
 
 bool backward_supported(const pn_ctx* c, bool fp32) {
   const Dims& d = c->d;
-  if (filt_fsz(d) > (size_t)32 * kThreads) return false;
+  if ((d.K / 16 + d.DZ / 16) * (d.DZ / 16) > 8 * (kThreads / 64)) return false;  // accumulator tiles per wave
   size_t lds = fp32 ? bwd_net_lds<float>(d, bwd_wb<float>(d)) : bwd_net_lds<double>(d, bwd_wb<double>(d));
   return lds <= 160 * 1024;
 }
