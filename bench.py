@@ -52,58 +52,30 @@ def tangent_flops_per_walker(s, net, T):
 
 def chunk_T(s, net, prec):
     """Same chunk choice as the library's planner (LDS budget per block)."""
-    N, DX, DZ = s.n_elec, net.dim_x, net.dim_z
+    N, DX, DZ, NN = s.n_elec, net.dim_x, net.dim_z, s.n_nuc
+    n_ee = N * (N - 1) // 2
     tn = 8 if prec == "fp64" else 4
     pad = 16 // tn
     LDX, LDZ = DX + pad, DZ + pad
     LDHZ = max(2 * LDZ, LDX)
-    for nc in range(1, 3 * N + 1):
-        T = -(-3 * N // nc)
-        if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
-            continue
+
+    def lds(T, stage):
         C = T + 1
         R = N * C
         NCE = min(N, T // 3 + 2)
-        lds = (3 * 64 * 8 + ((N * N + 3) & ~3) * 4
-               + (N * DZ + R * (LDX + LDHZ) + 2 * C * LDX + NCE * (N + s.n_nuc) * 4) * tn)
-        if lds <= 80 * 1024 or T == 1:
-            return T
+        e = N * DZ + R * (LDX + LDHZ) + 2 * C * LDX + NCE * (N + NN) * 4
+        if stage:
+            e += n_ee * DZ + 2 * NCE * (N + NN) * DZ
+        return 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + e * tn
+
+    for stage in (True, False):
+        for nc in range(1, 3 * N + 1):
+            T = -(-3 * N // nc)
+            if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
+                continue
+            if lds(T, stage) <= 112 * 1024 or (not stage and T == 1):
+                return T
     return 1
-
-
-def time_path(ctx, r, th, prec, steps, warmup, torch):
-    out = ctx.eval(r, th, prec)
-    ws = ctx.workspace(r.shape[0], prec, r.device)
-    for _ in range(warmup):
-        ctx.eval(r, th, prec, out=out, ws=ws)
-    torch.cuda.synchronize()
-    ctx.stage_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.eval(r, th, prec, out=out, ws=ws)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stages = ctx.stage_times()
-    ctx.stage_timing(False)
-    return dt, out, stages
-
-
-def cpu_baseline(workload_idx, budget_s=15.0, chunk=8):
-    import torch
-    from oracle import Oracle
-    from synth import make_config
-    w = make_config(workload_idx)
-    o = Oracle(w.system, w.net, w.params)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        o.evaluate(w.walkers[n:n + chunk])
-        n += chunk
-        if time.perf_counter() - t0 > budget_s or n >= w.walkers.shape[0]:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "walker-evals/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"first {n} walkers of the same workload, {chunk} per call, {dt:.1f} s"}
 
 
 def time_vmc_step(pn, ctx, w, prec, steps, warmup, torch):

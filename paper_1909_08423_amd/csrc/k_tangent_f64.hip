@@ -1,0 +1,28 @@
+// Network tangent pass, FP64 network; also the chunk planner helpers.
+#include "k_tangent_impl.h"
+
+namespace pn {
+
+// Chunk sizes T the kernel is instantiated for (columns C = T + 1).
+bool tangent_chunk_supported(int T) {
+  switch (T) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 9: case 10: case 12: case 15: return true;
+    default: return false;
+  }
+}
+
+template <typename TN>
+size_t tangent_lds_bytes(const Dims& d, int T, bool stage) {
+  const int C = T + 1, R = d.N * C;
+  const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
+  const int NCE = std::min(d.N, T / 3 + 2);  // electrons a chunk of T coordinates can touch
+  size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX + (size_t)NCE * (d.N + d.NN) * 4;
+  if (stage) tn += (size_t)d.n_ee * d.DZ + 2 * (size_t)NCE * (d.N + d.NN) * d.DZ;
+  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN);
+}
+
+template size_t tangent_lds_bytes<double>(const Dims&, int, bool);
+template size_t tangent_lds_bytes<float>(const Dims&, int, bool);
+template void launch_net_tangent<double>(const pn_ctx*, hipStream_t, int64_t, const double*, const double*, char*,
+                                         const WsLayout&, bool);
+}  // namespace pn

@@ -22,6 +22,14 @@
 // The values (h, w, w'/d, w'', ssp', ssp'') come from the value pass.  The
 // dense products run on the matrix cores (mfma_gemm.h); the message sums are
 // register-blocked over the C columns, which are a template parameter.
+// With STAGE the layer's filter values and the chunk electrons' filter
+// derivatives are copied to LDS first (coalesced), so the message sums read
+// only LDS; without it (systems whose pair tables do not fit) they read the
+// value pass's output in global memory.
+//
+// This file is included by k_tangent_f32.hip and k_tangent_f64.hip, which
+// instantiate it for one network type each.
+#pragma once
 #include "gemm_lds.h"
 #include "mfma_gemm.h"
 #include "pn_internal.h"
@@ -32,7 +40,7 @@ constexpr int kThreadsT = 512;
 
 namespace {
 
-template <typename TN, int C>
+template <typename TN, int C, bool STAGE>
 __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
                                                            const double* __restrict__ r, const TN* __restrict__ P,
                                                            ParamLayout pl, const TN* __restrict__ filt,
@@ -70,6 +78,10 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
   TN* ES = HT + R * LDHZ;                                       // [2][C][LDX]
   TN* cg = ES + 2 * C * LDX;                                    // [NCE][N][4]  r_i - r_k, 1/|r_i - r_k|
   TN* cgn = cg + NCE * N * 4;                                   // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
+  const int NP = N + d.NN;                                      // partners of a chunk electron
+  TN* wvs = cgn + NCE * d.NN * 4;                               // [n_ee][DZ]      (STAGE) w, all ee pairs
+  TN* wds = wvs + (STAGE ? d.n_ee * DZ : 0);                    // [NCE][NP][DZ]   (STAGE) w'/d
+  TN* w2s = wds + (STAGE ? NCE * NP * DZ : 0);                   // [NCE][NP][DZ]   (STAGE) w''
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
@@ -101,6 +113,15 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
     const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
     const TN* hv = hval + (w * d.L + n) * N * DZ;
     for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) hvs[q] = hv[q];
+    if constexpr (STAGE) {
+      for (int q = threadIdx.x; q < d.n_ee * DZ; q += blockDim.x) wvs[q] = fv[q];
+      for (int q = threadIdx.x; q < NCE * NP * DZ; q += blockDim.x) {
+        const int k = e_lo + q / (NP * DZ), part = (q / DZ) % NP, z = q % DZ;
+        const int64_t p = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
+        wds[q] = p >= 0 ? fd[p * DZ + z] : TN(0);
+        w2s[q] = p >= 0 ? f2[p * DZ + z] : TN(0);
+      }
+    }
     if (n > 0) gemm_mfma<TN>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
     __syncthreads();
     for (int ch = 0; ch < 2; ++ch) {
@@ -116,7 +137,7 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
         if (n > 0) {
           for (int j = j_lo; j < j_hi; ++j) {
             if (j == i) continue;
-            const TN wv = fv[(int64_t)pidx[i * N + j] * DZ + z];
+            const TN wv = STAGE ? wvs[pidx[i * N + j] * DZ + z] : fv[(int64_t)pidx[i * N + j] * DZ + z];
             const TN* hj = HT + (size_t)j * C * LDZ + z;
 #pragma unroll
             for (int c = 0; c < C; ++c) acc[c] += wv * hj[c * LDZ];
@@ -131,8 +152,15 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
           TN sv0 = 0, sv1 = 0, sv2 = 0;
           for (int j = j_lo; j < j_hi; ++j) {
             if (j == i) continue;
-            const int64_t p = pidx[i * N + j];
-            const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+            TN wd, w2;
+            if constexpr (STAGE) {
+              wd = wds[((i - e_lo) * NP + j) * DZ + z];
+              w2 = w2s[((i - e_lo) * NP + j) * DZ + z];
+            } else {
+              const int64_t p = pidx[i * N + j];
+              wd = fd[p * DZ + z];
+              w2 = f2[p * DZ + z];
+            }
             const TN hj = hvs[j * DZ + z];
             const TN inv = gi[4 * j + 3];
             const TN* hjc = HT + (size_t)j * C * LDZ + z;
@@ -163,9 +191,16 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
         // sources from the coordinates of the chunk's other electrons k
         for (int k = max(e_lo, j_lo); k <= min(e_hi, j_hi - 1); ++k) {
           if (k == i) continue;
-          const int64_t p = pidx[i * N + k];
           const TN* gk = cg + ((size_t)(k - e_lo) * N + i) * 4;  // r_i - r_k
-          const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+          TN wd, w2;
+          if constexpr (STAGE) {
+            wd = wds[((k - e_lo) * NP + i) * DZ + z];
+            w2 = w2s[((k - e_lo) * NP + i) * DZ + z];
+          } else {
+            const int64_t p = pidx[i * N + k];
+            wd = fd[p * DZ + z];
+            w2 = f2[p * DZ + z];
+          }
           const TN hk = hvs[k * DZ + z];
           const TN* hkc = HT + (size_t)k * C * LDZ + z;
 #pragma unroll
@@ -195,10 +230,17 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
       for (int c = 0; c < C; ++c) acc[c] = 0;
       const int c0 = 3 * i - a0;
       for (int I = 0; I < d.NN; ++I) {
-        const int64_t p = d.n_ee + i * d.NN + I;
         const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
         const TN y = P[pl.Y + I * DZ + z];
-        const TN wd = fd[p * DZ + z], w2 = f2[p * DZ + z];
+        TN wd, w2;
+        if constexpr (STAGE) {
+          wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
+          w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
+        } else {
+          const int64_t p = d.n_ee + i * d.NN + I;
+          wd = fd[p * DZ + z];
+          w2 = f2[p * DZ + z];
+        }
 #pragma unroll
         for (int c = 0; c < T; ++c) {
           const int al = c - c0;
@@ -291,64 +333,48 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
   }
 }
 
-template <typename TN, int C>
+template <typename TN, int C, bool STAGE>
 void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
               bool bf16) {
   const int64_t nb = nw * L.n_chunks;
   if (L.lds_tangent > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_net_tangent<TN, C>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_net_tangent<TN, C, STAGE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_tangent);
-  hipLaunchKernelGGL((k_net_tangent<TN, C>), dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d, c->t, nw,
-                     L.n_chunks, r, P, c->pl, reinterpret_cast<const TN*>(ws + L.filt),
+  hipLaunchKernelGGL((k_net_tangent<TN, C, STAGE>), dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d,
+                     c->t, nw, L.n_chunks, r, P, c->pl, reinterpret_cast<const TN*>(ws + L.filt),
                      reinterpret_cast<const TN*>(ws + L.hval), reinterpret_cast<const TN*>(ws + L.kcoef),
                      reinterpret_cast<const TN*>(ws + L.ecoef), reinterpret_cast<double*>(ws + L.ftan),
                      reinterpret_cast<double*>(ws + L.jtan), bf16);
 }
 
-}  // namespace
-
-// Chunk sizes T the kernel is instantiated for (columns C = T + 1).
-bool tangent_chunk_supported(int T) {
-  switch (T) {
-    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 9: case 10: case 12: case 15: return true;
-    default: return false;
-  }
-}
-
-template <typename TN>
-size_t tangent_lds_bytes(const Dims& d, int T) {
-  const int C = T + 1, R = d.N * C;
-  const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
-  const int NCE = std::min(d.N, T / 3 + 2);  // electrons a chunk of T coordinates can touch
-  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
-         ((size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX + (size_t)NCE * (d.N + d.NN) * 4) *
-             sizeof(TN);
-}
-
-template <typename TN>
-void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
-                        const WsLayout& L, bool bf16) {
+template <typename TN, bool STAGE>
+void launch_t(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
+              bool bf16) {
   switch (L.T + 1) {
-    case 2: launch_c<TN, 2>(c, s, nw, r, P, ws, L, bf16); break;
-    case 3: launch_c<TN, 3>(c, s, nw, r, P, ws, L, bf16); break;
-    case 4: launch_c<TN, 4>(c, s, nw, r, P, ws, L, bf16); break;
-    case 5: launch_c<TN, 5>(c, s, nw, r, P, ws, L, bf16); break;
-    case 6: launch_c<TN, 6>(c, s, nw, r, P, ws, L, bf16); break;
-    case 7: launch_c<TN, 7>(c, s, nw, r, P, ws, L, bf16); break;
-    case 9: launch_c<TN, 9>(c, s, nw, r, P, ws, L, bf16); break;
-    case 10: launch_c<TN, 10>(c, s, nw, r, P, ws, L, bf16); break;
-    case 11: launch_c<TN, 11>(c, s, nw, r, P, ws, L, bf16); break;
-    case 13: launch_c<TN, 13>(c, s, nw, r, P, ws, L, bf16); break;
-    case 16: launch_c<TN, 16>(c, s, nw, r, P, ws, L, bf16); break;
+    case 2: launch_c<TN, 2, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 3: launch_c<TN, 3, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 4: launch_c<TN, 4, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 5: launch_c<TN, 5, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 6: launch_c<TN, 6, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 7: launch_c<TN, 7, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 9: launch_c<TN, 9, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 10: launch_c<TN, 10, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 11: launch_c<TN, 11, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 13: launch_c<TN, 13, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 16: launch_c<TN, 16, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
     default: break;  // the planner only picks supported chunk sizes
   }
 }
 
-template size_t tangent_lds_bytes<double>(const Dims&, int);
-template size_t tangent_lds_bytes<float>(const Dims&, int);
-template void launch_net_tangent<double>(const pn_ctx*, hipStream_t, int64_t, const double*, const double*, char*,
-                                         const WsLayout&, bool);
-template void launch_net_tangent<float>(const pn_ctx*, hipStream_t, int64_t, const double*, const float*, char*,
-                                        const WsLayout&, bool);
+}  // namespace
+
+template <typename TN>
+void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                        const WsLayout& L, bool bf16) {
+  if (L.stage_filters)
+    launch_t<TN, true>(c, s, nw, r, P, ws, L, bf16);
+  else
+    launch_t<TN, false>(c, s, nw, r, P, ws, L, bf16);
+}
 
 }  // namespace pn

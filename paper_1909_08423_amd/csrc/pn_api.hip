@@ -12,7 +12,7 @@
 namespace pn {
 
 template <typename TN>
-size_t tangent_lds_bytes(const Dims& d, int T);
+size_t tangent_lds_bytes(const Dims& d, int T, bool stage);
 template <typename TN>
 size_t value_lds_bytes(const Dims& d, int wpb);
 size_t slater_tangent_lds_bytes(const Dims& d, int T);
@@ -123,21 +123,29 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   const bool fp64 = prec == PN_PREC_FP64;
   const size_t tn = fp64 ? sizeof(double) : sizeof(float);
   WsLayout L{};
-  // chunking of the 3N coordinates for the tangent pass
-  const size_t budget = 80 * 1024;
+  // chunking of the 3N coordinates for the tangent pass: the largest chunk
+  // whose block fits the LDS budget, preferring the form that stages the
+  // filter tables in LDS
+  const size_t budget = 112 * 1024;
   const int ncoord = 3 * d.N;
-  L.T = 1;
-  for (int nc = 1; nc <= ncoord; ++nc) {
-    int T = (ncoord + nc - 1) / nc;
-    if (!tangent_chunk_supported(T)) continue;
-    size_t lds = fp64 ? tangent_lds_bytes<double>(d, T) : tangent_lds_bytes<float>(d, T);
-    if (lds <= budget || T == 1) {
-      L.T = T;
-      break;
+  auto lds_of = [&](int T, bool stage) {
+    return fp64 ? tangent_lds_bytes<double>(d, T, stage) : tangent_lds_bytes<float>(d, T, stage);
+  };
+  L.T = 0;
+  for (int pass = 0; pass < 2 && L.T == 0; ++pass) {
+    const bool stage = pass == 0;
+    for (int nc = 1; nc <= ncoord; ++nc) {
+      const int T = (ncoord + nc - 1) / nc;
+      if (!tangent_chunk_supported(T)) continue;
+      if (lds_of(T, stage) <= budget || (!stage && T == 1)) {
+        L.T = T;
+        L.stage_filters = stage;
+        break;
+      }
     }
   }
   L.n_chunks = (ncoord + L.T - 1) / L.T;
-  L.lds_tangent = fp64 ? tangent_lds_bytes<double>(d, L.T) : tangent_lds_bytes<float>(d, L.T);
+  L.lds_tangent = lds_of(L.T, L.stage_filters);
   L.wpb_value = std::max(1, 64 / d.N);
   while (L.wpb_value > 1 &&
          (fp64 ? value_lds_bytes<double>(d, L.wpb_value) : value_lds_bytes<float>(d, L.wpb_value)) > 64 * 1024)

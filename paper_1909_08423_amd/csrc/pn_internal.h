@@ -80,6 +80,7 @@ struct WsLayout {
   size_t lds_value;
   size_t lds_filter;
   int filt_rows;       // pairs per block in the filter kernel
+  bool stage_filters;  // tangent pass copies the layer's filter tables to LDS
   // offsets
   size_t params_net;   // converted params (float) when the network is FP32/BF16
   size_t geo;          // [tile][GEO] V, gamma, then per electron grad(3) + hess diag(3)

@@ -105,7 +105,7 @@ def test_antisymmetry_on_gpu(pn):
     np.testing.assert_allclose(b["eloc"], a["eloc"], rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 1e-3), (3, "fp32", 1e-3), (2, "bf16", 0.2), (3, "bf16", 0.2)])
+@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 1e-3), (3, "fp32", 1e-3), (5, "fp32", 1e-3), (2, "bf16", 0.2), (3, "bf16", 0.2)])
 def test_mixed_precision_error_statement(pn, idx, prec, bound):
     """Mixed modes: the network in FP32 (or BF16 operands with FP32
     accumulation), determinants and E_loc in FP64.  The per-output error
