@@ -78,6 +78,41 @@ def chunk_T(s, net, prec):
     return 1
 
 
+def time_path(ctx, r, th, prec, steps, warmup, torch):
+    out = ctx.eval(r, th, prec)
+    ws = ctx.workspace(r.shape[0], prec, r.device)
+    for _ in range(warmup):
+        ctx.eval(r, th, prec, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ctx.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.eval(r, th, prec, out=out, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.stage_timing(False)
+    return dt, out, stages
+
+
+def cpu_baseline(workload_idx, budget_s=15.0, chunk=8):
+    import torch
+    from oracle import Oracle
+    from synth import make_config
+    w = make_config(workload_idx)
+    o = Oracle(w.system, w.net, w.params)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.evaluate(w.walkers[n:n + chunk])
+        n += chunk
+        if time.perf_counter() - t0 > budget_s or n >= w.walkers.shape[0]:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "walker-evals/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"first {n} walkers of the same workload, {chunk} per call, {dt:.1f} s"}
+
+
 def time_vmc_step(pn, ctx, w, prec, steps, warmup, torch):
     """Full VMC step of one job (Metropolis + E_loc + clipping + gradient +
     AdamW) on the benchmark batch."""
