@@ -73,7 +73,7 @@ def chunk_T(s, net, prec):
             T = -(-3 * N // nc)
             if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
                 continue
-            if lds(T, stage) <= 112 * 1024 or (not stage and T == 1):
+            if lds(T, stage) <= 80 * 1024 or (not stage and T == 1):
                 return T
     return 1
 

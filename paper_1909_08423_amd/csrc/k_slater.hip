@@ -199,6 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_combine_value(Dims d, DevTables t,
   sign[w] = S > 0 ? 1.0 : -1.0;
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
                                                              const double* __restrict__ geo,
                                                              const double* __restrict__ phi,
@@ -219,10 +220,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
   double* TB = reinterpret_cast<double*>(smem);       // [C][M][N] table derivatives
   double* gres = TB + (size_t)C * M * N;              // [P][2][T]
   double* dres = gres + (size_t)P * 2 * T;            // [P][2]
-  double* scr = dres + (size_t)P * 2;                 // per wave: G, Tm, Mm  (3 * NM * NM)
-  double* Gw = scr + (size_t)wv * 3 * NM * NM;
-  double* Tw = Gw + NM * NM;
-  double* Mw = Tw + NM * NM;
+  double* scr = dres + (size_t)P * 2;                 // per wave scratch, SW doubles
+  const int SW = C * NM * NM + 2 * C * NM;
 
   const double* ph = phi + w * N * M * 7;
   const double* fv = fval + w * N * M;
@@ -248,7 +247,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
     }
   }
   __syncthreads();
-  // per (determinant, spin), one wavefront each
+  // per (determinant, spin), one wavefront each; its lanes take (column,
+  // row x) pairs and form row x of M_a = G T_a for all columns at once
   const int gsz = d.n_up * d.n_up + d.n_dn * d.n_dn;
   for (int ps = wv; ps < P * 2; ps += kWaves) {
     const int p = ps / 2, spin = ps % 2;
@@ -262,44 +262,56 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
       continue;
     }
     const double* Gg = ginv + (w * P + p) * gsz + (spin == 0 ? 0 : d.n_up * d.n_up);
-    for (int q = lane; q < n * n; q += 64) Gw[q] = Gg[q];
-    wave_sync();
-    double sq_total = 0.0;
-    for (int col = 0; col < C; ++col) {
-      const double* tb = TB + (size_t)col * M * N;
-      for (int q = lane; q < n * n; q += 64) {
-        int k = q / n, i = q % n;
-        Tw[q] = tb[occ[k] * N + e0 + i];
+    double* Ms = scr + (size_t)wv * SW;     // [C][n][n] rows of M_a
+    double* gpart = Ms + (size_t)C * NM * NM;  // [C][n] diagonal of M_a, or tr(G L) parts
+    double* qpart = gpart + (size_t)C * NM;    // [C][n] sum_y M[x][y] M[y][x]
+    for (int it = lane; it < C * n; it += 64) {
+      const int col = it / n, x = it % n;
+      const double* tb = TB + (size_t)col * M * N + e0;
+      double row[NMAX];
+#pragma unroll
+      for (int y = 0; y < NMAX; ++y) row[y] = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double gxk = Gg[x * n + k];
+        const double* tk = tb + (size_t)occ[k] * N;
+#pragma unroll
+        for (int y = 0; y < NMAX; ++y)
+          if (y < n) row[y] += gxk * tk[y];
       }
-      wave_sync();
-      if (col == LC) {
-        // tr(G L) = sum_{x,k} G[x][k] L[k][x]
-        double v = 0.0;
-        for (int q = lane; q < n * n; q += 64) v += Gw[q] * Tw[(q % n) * n + q / n];
-        v = wave_sum(v);
-        if (lane == 0) dres[ps] = v - sq_total;
-      } else {
-        // M = G T ; tr(M) and tr(M^2)
-        for (int q = lane; q < n * n; q += 64) {
-          int x = q / n, y = q % n;
-          double v = 0.0;
-          for (int k = 0; k < n; ++k) v += Gw[x * n + k] * Tw[k * n + y];
-          Mw[q] = v;
-        }
-        wave_sync();
-        double tr = 0.0, tr2 = 0.0;
-        for (int q = lane; q < n * n; q += 64) {
-          int x = q / n, y = q % n;
-          if (x == y) tr += Mw[q];
-          tr2 += Mw[q] * Mw[y * n + x];
-        }
-        tr = wave_sum(tr);
-        tr2 = wave_sum(tr2);
-        sq_total += tr2;
-        if (lane == 0) gr[col] = tr;
-      }
-      wave_sync();
+      double* mr = Ms + ((size_t)col * n + x) * n;
+#pragma unroll
+      for (int y = 0; y < NMAX; ++y)
+        if (y < n) mr[y] = row[y];
     }
+    wave_sync();
+    for (int it = lane; it < C * n; it += 64) {
+      const int col = it / n, x = it % n;
+      const double* mc = Ms + (size_t)col * n * n;
+      gpart[col * n + x] = mc[x * n + x];  // the Laplacian column gives tr(G L)
+      double q = 0.0;
+      if (col != LC)
+        for (int y = 0; y < n; ++y) q += mc[x * n + y] * mc[y * n + x];
+      qpart[col * n + x] = q;
+    }
+    wave_sync();
+    double sq = 0.0;
+    for (int col = lane; col < C; col += 64) {
+      double tr = 0.0, q = 0.0;
+      for (int x = 0; x < n; ++x) {
+        tr += gpart[col * n + x];
+        q += qpart[col * n + x];
+      }
+      if (col < LC) {
+        gr[col] = tr;
+        sq += q;
+      } else {
+        dres[ps] = tr;  // tr(G L)
+      }
+    }
+    sq = wave_sum(sq);
+    wave_sync();
+    if (lane == 0) dres[ps] -= sq;
+    wave_sync();
   }
   __syncthreads();
   // determinant sum per coordinate, then gamma and J
@@ -367,7 +379,8 @@ void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, c
 
 size_t slater_tangent_lds_bytes(const Dims& d, int T) {
   const int C = T + 1, NM = std::max(std::max(d.n_up, d.n_dn), 1);
-  return ((size_t)C * d.M * d.N + (size_t)d.P * 2 * T + d.P * 2 + (size_t)kWaves * 3 * NM * NM) * sizeof(double);
+  return ((size_t)C * d.M * d.N + (size_t)d.P * 2 * T + d.P * 2 + (size_t)kWaves * (C * NM * NM + 2 * C * NM)) *
+         sizeof(double);
 }
 
 void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws, const WsLayout& L,
@@ -375,15 +388,24 @@ void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
   const Dims& d = c->d;
   (void)r;
   size_t lds = slater_tangent_lds_bytes(d, L.T);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_slater_tangent),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_slater_tangent, dim3((unsigned)(nw * L.n_chunks)), dim3(kThreads), lds, s, d, c->t, nw, L.T,
-                     L.n_chunks, reinterpret_cast<const double*>(ws + L.geo),
-                     reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
-                     reinterpret_cast<const double*>(ws + L.ftan), reinterpret_cast<const double*>(ws + L.jtan),
-                     reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet),
-                     grad, reinterpret_cast<double*>(ws + L.partial));
+  const int NM = std::max(d.n_up, d.n_dn);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nw * L.n_chunks)), dim3(kThreads), lds, s, d, c->t, nw, L.T,
+                       L.n_chunks, reinterpret_cast<const double*>(ws + L.geo),
+                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
+                       reinterpret_cast<const double*>(ws + L.ftan), reinterpret_cast<const double*>(ws + L.jtan),
+                       reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet),
+                       grad, reinterpret_cast<double*>(ws + L.partial));
+  };
+  if (NM <= 8)
+    go(&k_slater_tangent<8>);
+  else if (NM <= 16)
+    go(&k_slater_tangent<16>);
+  else
+    go(&k_slater_tangent<32>);
 }
 
 void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* grad,

@@ -3,7 +3,8 @@
 // respect to one chunk of electron coordinates (Methods, "PauliNet
 // extension of SchNet"; Results, J = eta(sum_i x_i), f_i = kappa(x_i)).
 //
-// One block per (walker, chunk).  The chunk holds T = C - 1 coordinates
+// One 256-thread block per (walker, chunk); two blocks share a CU, so one
+// block's barriers and load latencies overlap the other's work.  The chunk holds T = C - 1 coordinates
 // a = a0 .. a0 + T - 1 (the last chunk may be ragged; its missing
 // coordinates are zero columns).  For every electron row i the block keeps,
 // in LDS, the T derivative columns d x_i / d r_a and one column with
@@ -36,7 +37,7 @@
 
 namespace pn {
 
-constexpr int kThreadsT = 512;
+constexpr int kThreadsT = 256;
 
 namespace {
 

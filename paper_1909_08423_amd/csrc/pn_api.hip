@@ -126,7 +126,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   // chunking of the 3N coordinates for the tangent pass: the largest chunk
   // whose block fits the LDS budget, preferring the form that stages the
   // filter tables in LDS
-  const size_t budget = 112 * 1024;
+  const size_t budget = 80 * 1024;  // two 256-thread blocks per CU
   const int ncoord = 3 * d.N;
   auto lds_of = [&](int T, bool stage) {
     return fp64 ? tangent_lds_bytes<double>(d, T, stage) : tangent_lds_bytes<float>(d, T, stage);
