@@ -78,6 +78,52 @@ def chunk_T(s, net, prec):
     return 1
 
 
+TANGENT_SOURCES = ["k_tangent_impl.h", "k_tangent_f32.hip", "k_tangent_f64.hip", "mfma_gemm.h", "gemm_lds.h"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_net_tangent_ne4096_counters.md")
+
+
+def tangent_source_digest():
+    """sha256 over the sources of the tangent kernel (counters taken on
+    another build of it do not describe this one)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TANGENT_SOURCES:
+        with open(os.path.join(ROOT, "paper_1909_08423_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(prec, T, B):
+    """HBM bytes per launch of the tangent kernel from the committed counter
+    summary, or None when that summary was taken on other kernel sources or
+    another launch configuration."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+            if (rec.get("sha256") == tangent_source_digest() and rec.get("prec") == prec
+                    and rec.get("chunk_coords") == T and rec.get("walkers") == B):
+                return rec["hbm_bytes_per_launch"]
+    return None
+
+
+def copy_probe(mib, torch):
+    """A plain device-to-device copy of known size, run so that a counter
+    pass over this program also reads the counters for it (the scale factor
+    of FETCH_SIZE / WRITE_SIZE against bytes actually moved)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "reps": 3}
+
+
 def time_path(ctx, r, th, prec, steps, warmup, torch):
     out = ctx.eval(r, th, prec)
     ws = ctx.workspace(r.shape[0], prec, r.device)
@@ -173,6 +219,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the walker batch shards "
@@ -187,6 +235,7 @@ def main():
         print("no ROCm device", file=sys.stderr)
         sys.exit(1)
     pn.load_library()
+    probe = copy_probe(args.copy_probe, torch) if args.copy_probe > 0 else None
     w = make_config(args.workload)
     s, net = w.system, w.net
     B = w.walkers.shape[0]
@@ -223,7 +272,8 @@ def main():
         peak = PEAKS["fp64" if args.prec == "fp64" else ("bf16" if args.prec == "bf16" else "fp32")]
         ach = fl / (avg_ms * 1e-3) / 1e12
         roof = {"kernel": "k_net_tangent", "bound": "alu" if args.prec != "bf16" else "mfma",
-                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": stored_traffic(args.prec, T, B),
                 "flops_per_walker": fl / B, "avg_launch_ms": avg_ms, "chunk_coords": T}
     else:
         roof = {"kernel": dom, "bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
@@ -252,6 +302,8 @@ def main():
         "stages_ms_per_step_fp64": {k: v[0] / max(v[1], 1) for k, v in st_64.items() if v[1] > 0},
         "roofline": roof,
     }
+    if probe is not None:
+        res["copy_probe"] = probe
     res["vmc_step"] = time_vmc_step(pn, ctx, w, P[args.prec], max(3, args.steps // 4), 1, torch)
     if not args.no_serve:
         res["serving"] = run_serving(pn, P[args.prec], args.serve_jobs, args.serve_steps, torch)
