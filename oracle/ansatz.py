@@ -117,6 +117,39 @@ class Oracle:
         g, lap, el = local_energy_from(lambda x: self.log_psi(x)[0], self.potential, r)
         return {"logabs": lp, "sign": sg, "grad": g, "lap": lap, "eloc": el}
 
+    def param_grad_full(self, r, ct_logabs=None, ct_grad=None, ct_lap=None, ct_eloc=None):
+        """sum_w of the cotangents times the parameter derivatives of the
+        outputs: ln|psi_w|, its coordinate gradient [N,3], its Laplacian and
+        E_loc (each cotangent may be None = zero).  V does not depend on the
+        parameters, so d E_loc / d theta = -1/2 d(lap + |grad|^2) / d theta:
+        the Laplacian's second-order terms enter through a third autograd
+        level (the Laplacian graph is kept with create_graph)."""
+        r = torch.as_tensor(r, dtype=torch.float64)
+        B = r.shape[0]
+        th = self.flat.detach().clone().requires_grad_(True)
+        rr = r.detach().clone().requires_grad_(True)
+        lp, _ = self.log_psi(rr, th)
+        (g,) = torch.autograd.grad(lp.sum(), rr, create_graph=True)
+        gf = g.reshape(B, -1)
+        lap = torch.zeros(B, dtype=torch.float64)
+        for a in range(gf.shape[1]):
+            (h,) = torch.autograd.grad(gf[:, a].sum(), rr, create_graph=True)
+            lap = lap + h.reshape(B, -1)[:, a]
+        loss = torch.zeros((), dtype=torch.float64)
+        t = lambda x: torch.as_tensor(x, dtype=torch.float64)
+        if ct_logabs is not None:
+            loss = loss + (t(ct_logabs) * lp).sum()
+        if ct_grad is not None:
+            loss = loss + (t(ct_grad).reshape(B, -1) * gf).sum()
+        if ct_lap is not None:
+            loss = loss + (t(ct_lap) * lap).sum()
+        if ct_eloc is not None:
+            loss = loss + (t(ct_eloc) * (-0.5) * (lap + (gf ** 2).sum(-1))).sum()
+        if not loss.requires_grad:
+            return torch.zeros_like(th)
+        (gth,) = torch.autograd.grad(loss, th)
+        return gth
+
     def param_grad_logabs(self, r, cotangent):
         """sum_w cotangent_w * d ln|psi_w| / d theta (value-path adjoint)."""
         r = torch.as_tensor(r, dtype=torch.float64)

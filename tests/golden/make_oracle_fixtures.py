@@ -1,6 +1,7 @@
 """Write the oracle reference values used by the GPU parity tests.
 
-    python tests/golden/make_oracle_fixtures.py
+    python tests/golden/make_oracle_fixtures.py            (forward, value adjoint)
+    python tests/golden/make_oracle_fixtures.py --full     (full adjoint)
 
 Inputs come from the seeded generators in `synth`; expected values come only
 from the CPU oracle in `oracle/`.  Nothing here touches the HIP library.
@@ -74,6 +75,36 @@ def run(idx):
     print(f"cfg {idx}: {walkers.shape[0]} + {n_sample} walkers in {time.time() - t0:.1f}s -> {path}")
 
 
+# full adjoint (cotangents on ln|psi|, grad, lap and E_loc): workload -> walkers
+FULL_PLAN = {1: 6, 2: 5, 3: 4}
+
+
+def run_full(idx):
+    """Parameter gradients of sum_w ct . (ln|psi|, grad, lap, E_loc) for four
+    cotangent sets: gradient only, Laplacian only, E_loc only, all four."""
+    nb = FULL_PLAN[idx]
+    w = make_config(idx, n_walkers=67)
+    o = Oracle(w.system, w.net, w.params)
+    walkers = np.concatenate([w.walkers[:nb - 1], special_walkers(w, w.walkers[0])[:1]])
+    B, N = walkers.shape[0], walkers.shape[1]
+    rng = np.random.default_rng(900 + idx)
+    ca, cg, cl, ce = rng.standard_normal(B), rng.standard_normal((B, N, 3)), rng.standard_normal(B), \
+        rng.standard_normal(B)
+    t0 = time.time()
+    sets = {"grad": (None, cg, None, None), "lap": (None, None, cl, None), "eloc": (None, None, None, ce),
+            "all": (ca, cg, cl, ce)}
+    res = {k: o.param_grad_full(walkers, *v).numpy() for k, v in sets.items()}
+    path = os.path.join(HERE, f"oracle_full_adjoint_cfg{idx}.npz")
+    np.savez_compressed(path, walkers=walkers, ct_logabs=ca, ct_grad=cg, ct_lap=cl, ct_eloc=ce,
+                        **{"g_" + k: v for k, v in res.items()})
+    print(f"cfg {idx} full adjoint: {B} walkers in {time.time() - t0:.1f}s -> {path}")
+
+
 if __name__ == "__main__":
-    for idx in (int(a) for a in sys.argv[1:]) if len(sys.argv) > 1 else PLAN:
-        run(idx)
+    args = sys.argv[1:]
+    if args and args[0] == "--full":
+        for idx in (int(a) for a in args[1:]) if len(args) > 1 else FULL_PLAN:
+            run_full(idx)
+    else:
+        for idx in (int(a) for a in args) if args else PLAN:
+            run(idx)
