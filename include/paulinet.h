@@ -127,6 +127,12 @@ int64_t pn_param_count(const pn_ctx* ctx);
  * tile by tile, so the size stops growing at the tile. */
 pn_status pn_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
 
+/* Workspace bytes that also cover pn_eval_backward with cotangents on the
+ * gradient, Laplacian or local energy (the full adjoint keeps the layer
+ * inputs of the tangent pass and per-chunk cotangent tables per walker
+ * tile); never less than pn_workspace_bytes. */
+pn_status pn_workspace_bytes_full(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+
 /* Forward evaluation (the hot path).
  *   r       [B][n_elec][3] FP64 walker positions
  *   params  [pn_param_count] FP64 parameter blob (converted internally to
@@ -140,17 +146,29 @@ pn_status pn_eval(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers, cons
                   const double* params, pn_precision prec, double* logabs, double* sign,
                   double* grad, double* lap, double* eloc, void* ws, size_t ws_bytes);
 
-/* Value-path adjoint (Methods eq. "trainig" needs only the parameter
- * gradient of ln|psi|):
- *   grad_params[t] += sum_w ct_logabs[w] d ln|psi_w| / d theta_t
- * grad_params is [pn_param_count] FP64 and is ACCUMULATED into.  The
- * forward values are recomputed inside the call (nothing is stored between
- * calls).  Per-walker contributions are reduced in a fixed order, so the
- * result does not depend on what else runs on the device. */
+/* Parameter adjoint of the evaluation:
+ *   grad_params[t] += sum_w ( ct_logabs[w] d ln|psi_w| / d theta_t
+ *                           + sum_a ct_grad[w][a] d (d_a ln|psi_w|) / d theta_t
+ *                           + ct_lap[w] d (lap ln|psi_w|) / d theta_t
+ *                           + ct_eloc[w] d E_loc,w / d theta_t )
+ * Each cotangent pointer may be NULL (= zero); ct_grad is [B][n_elec][3],
+ * the others [B].  With only ct_logabs this is the value-path adjoint that
+ * the Hermitian gradient estimator needs (Methods eq. "trainig": weights
+ * 2 (E_loc - L) / B); with ct_grad, ct_lap or ct_eloc it is the full
+ * adjoint through the coordinate derivatives, the Laplacian's second-order
+ * terms included (d E_loc / d theta = -1/2 d(lap + |grad|^2) / d theta,
+ * since V does not depend on theta), and needs pn_workspace_bytes_full
+ * bytes of workspace.  grad_params is [pn_param_count] FP64 and is
+ * ACCUMULATED into.  The forward values are recomputed inside the call
+ * (nothing is stored between calls).  Per-walker contributions are reduced
+ * in a fixed order, so the result does not depend on what else runs on the
+ * device.  In the BF16 mode the forward recomputation uses BF16 operands and
+ * the adjoint products FP32.  Shapes whose adjoint blocks exceed the LDS
+ * limit return PN_ERR_UNSUPPORTED_SHAPE. */
 pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers,
                            const double* r, const double* params, pn_precision prec,
-                           const double* ct_logabs, double* grad_params, void* ws,
-                           size_t ws_bytes);
+                           const double* ct_logabs, const double* ct_grad, const double* ct_lap,
+                           const double* ct_eloc, double* grad_params, void* ws, size_t ws_bytes);
 
 /* ---- one VMC step of a job (serving) -------------------------------------
  * Methods, "Ansatz optimization": the walkers sample |psi|^2 by Metropolis

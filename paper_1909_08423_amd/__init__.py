@@ -14,6 +14,7 @@ from ._lib import (  # noqa: F401
     PauliNetError,
     library_path,
     load_library,
+    paulinet_eval,
     vmc_step,
     vmc_workspace_bytes,
 )

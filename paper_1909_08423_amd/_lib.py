@@ -110,7 +110,9 @@ def load_library():
     lib.pn_workspace_bytes.restype = i32
     lib.pn_eval.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.pn_eval.restype = i32
-    lib.pn_eval_backward.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, ctypes.c_size_t]
+    lib.pn_workspace_bytes_full.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_workspace_bytes_full.restype = i32
+    lib.pn_eval_backward.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.pn_eval_backward.restype = i32
     lib.pn_stage_timing.argtypes = [vp, i32]
     lib.pn_stage_timing.restype = i32
@@ -207,15 +209,16 @@ class PauliNetContext:
     def param_count(self):
         return int(self._lib.pn_param_count(self._ctx))
 
-    def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64):
+    def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64, full=False):
+        """Workspace bytes; full=True also covers the full adjoint."""
         b = ctypes.c_size_t()
-        _check(self._lib.pn_workspace_bytes(self._ctx, int(n_walkers), int(prec), ctypes.byref(b)),
-               "pn_workspace_bytes")
+        fn = self._lib.pn_workspace_bytes_full if full else self._lib.pn_workspace_bytes
+        _check(fn(self._ctx, int(n_walkers), int(prec), ctypes.byref(b)), "pn_workspace_bytes")
         return int(b.value)
 
-    def workspace(self, n_walkers, prec, device):
+    def workspace(self, n_walkers, prec, device, full=False):
         import torch
-        need = self.workspace_bytes(n_walkers, prec)
+        need = self.workspace_bytes(n_walkers, prec, full)
         key = (str(device),)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
@@ -259,21 +262,77 @@ class PauliNetContext:
         _check(st, "pn_eval")
         return out
 
-    def eval_backward(self, r, params, ct_logabs, prec=PN_PREC_FP64, grad_params=None, ws=None):
-        """grad_params += sum_w ct_logabs[w] d ln|psi_w| / d params."""
+    def eval_backward(self, r, params, ct_logabs=None, prec=PN_PREC_FP64, grad_params=None, ws=None,
+                      ct_grad=None, ct_lap=None, ct_eloc=None):
+        """grad_params += sum_w [ct_logabs d ln|psi| + ct_grad . d grad + ct_lap d lap
+        + ct_eloc d E_loc] / d params (each cotangent may be None = zero)."""
         import torch
         r = r.contiguous()
         params = params.contiguous()
-        ct_logabs = ct_logabs.contiguous().to(torch.float64)
         B = int(r.shape[0])
+
+        def prep(t, shape):
+            if t is None:
+                return None
+            t = t.to(torch.float64).contiguous()
+            if tuple(t.shape) != shape:
+                raise PauliNetError(f"cotangent of shape {tuple(t.shape)}, expected {shape}")
+            return t
+        ct_logabs = prep(ct_logabs, (B,))
+        ct_grad = prep(ct_grad, (B, self.n_elec, 3))
+        ct_lap = prep(ct_lap, (B,))
+        ct_eloc = prep(ct_eloc, (B,))
+        full = ct_grad is not None or ct_lap is not None or ct_eloc is not None
         if grad_params is None:
             grad_params = torch.zeros(self.param_count, dtype=torch.float64, device=r.device)
         if ws is None:
-            ws = self.workspace(B, prec, r.device)
+            ws = self.workspace(B, prec, r.device, full)
         st = self._lib.pn_eval_backward(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
-                                        _ptr(ct_logabs), _ptr(grad_params), _ptr(ws), ws.numel())
+                                        _ptr(ct_logabs), _ptr(ct_grad), _ptr(ct_lap), _ptr(ct_eloc),
+                                        _ptr(grad_params), _ptr(ws), ws.numel())
         _check(st, "pn_eval_backward")
         return grad_params
+
+
+def _autograd_function():
+    import torch
+
+    class PauliNetEval(torch.autograd.Function):
+        """(ln|psi|, sign, grad, lap, E_loc) = f(params) for fixed walkers;
+        the backward is the library's hand-written adjoint (pn_eval_backward
+        with the output cotangents, the Laplacian's second-order terms
+        included)."""
+
+        @staticmethod
+        def forward(fctx, params, r, pnctx, prec):
+            out = pnctx.eval(r.detach(), params.detach(), prec)
+            fctx.save_for_backward(params, r)
+            fctx.pnctx, fctx.prec = pnctx, prec
+            fctx.mark_non_differentiable(out["sign"])
+            return out["logabs"], out["sign"], out["grad"], out["lap"], out["eloc"]
+
+        @staticmethod
+        def backward(fctx, g_logabs, g_sign, g_grad, g_lap, g_eloc):
+            params, r = fctx.saved_tensors
+            gp = fctx.pnctx.eval_backward(r.detach(), params.detach(), g_logabs, fctx.prec, ct_grad=g_grad,
+                                          ct_lap=g_lap, ct_eloc=g_eloc)
+            return gp.to(params.dtype), None, None, None
+
+    return PauliNetEval
+
+
+_PNE = None
+
+
+def paulinet_eval(pnctx, r, params, prec=PN_PREC_FP64):
+    """Differentiable evaluation: returns (logabs, sign, grad, lap, eloc);
+    gradients flow to `params` (float64 device tensor) through the library's
+    adjoint.  Walker positions are inputs only (their derivatives are the
+    `grad` and `lap` outputs themselves)."""
+    global _PNE
+    if _PNE is None:
+        _PNE = _autograd_function()
+    return _PNE.apply(params, r, pnctx, prec)
 
 
 def vmc_workspace_bytes(ctx, n_walkers, prec):

@@ -21,6 +21,7 @@
 //  k_bwd_reduce  sums the slots in a fixed order into the FP64 gradient.
 // The fixed grids and slot order make the result independent of anything
 // else running on the device.
+#include "adj_util.h"
 #include "gemm_lds.h"
 #include "mfma_gemm.h"
 #include "pn_internal.h"
@@ -33,83 +34,16 @@ constexpr int kSlotsFilter = 256;  // blocks per (layer, channel) of k_bwd_filte
 constexpr int kFiltRows = 32;      // (walker, pair) rows per tile of k_bwd_filter
 
 template <typename TN>
-__device__ __forceinline__ TN sig(TN u) {
-  return sigmoid_d(u);
-}
-
-// slot[a*B + b] (+)= sum_r X[r][a] Y[r][b]
-template <typename TN>
-__device__ void outer_acc(const TN* X, int ldx, int A, const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
-  for (int q = threadIdx.x; q < A * B; q += blockDim.x) {
-    const int a = q / B, b = q % B;
-    TN s = 0;
-    for (int r = 0; r < rows; ++r) s += X[(size_t)r * ldx + a] * Y[(size_t)r * ldy + b];
-    slot[q] = first ? s : slot[q] + s;
-  }
-}
-// same with X replaced by ssp(U) (recomputed on the fly)
-template <typename TN>
-__device__ void outer_acc_ssp(const TN* U, int ldu, int A, const TN* Y, int ldy, int B, int rows, TN* slot,
-                              bool first) {
-  for (int q = threadIdx.x; q < A * B; q += blockDim.x) {
-    const int a = q / B, b = q % B;
-    TN s = 0;
-    for (int r = 0; r < rows; ++r) s += ssp(U[(size_t)r * ldu + a]) * Y[(size_t)r * ldy + b];
-    slot[q] = first ? s : slot[q] + s;
-  }
-}
-// slot[a*B + b] (+)= sum_r f(X[r][a]) Y[r][b] on the matrix cores (f = identity
-// or ssp); A and B multiples of 16.  Rows are reduced in chunks of 32: lane
-// group g takes rows g*8 .. g*8+7 of a chunk, rows past `rows` read as zero.
-template <typename TN, bool SSP>
-__device__ void outer_mfma(const TN* X, int ldx, int A, const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
-  typedef typename MfmaTile<TN>::acc_t acc_t;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-  const int nbt = B / 16, nt = (A / 16) * nbt;
-  for (int tt = wv; tt < nt; tt += nwv) {
-    const int a0 = (tt / nbt) * 16, b0 = (tt % nbt) * 16;
-    acc_t c;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) c[v] = 0;
-    for (int r0 = 0; r0 < rows; r0 += 32) {
-      TN af[8], bf[8];
-#pragma unroll
-      for (int s2 = 0; s2 < 8; ++s2) {
-        const int r = r0 + g * 8 + s2;
-        const bool ok = r < rows;
-        const TN xv = ok ? X[(size_t)r * ldx + a0 + c16] : TN(0);
-        af[s2] = SSP ? (ok ? ssp(xv) : TN(0)) : xv;
-        bf[s2] = ok ? Y[(size_t)r * ldy + b0 + c16] : TN(0);
-      }
-      c = MfmaChain<TN, 8>::run(af, bf, c, false);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const size_t q = (size_t)(a0 + MfmaTile<TN>::row_of(lane, v)) * B + b0 + c16;
-      slot[q] = first ? c[v] : slot[q] + c[v];
-    }
-  }
-}
-
-// slot[b] (+)= sum_r Y[r][b]
-template <typename TN>
-__device__ void colsum_acc(const TN* Y, int ldy, int B, int rows, TN* slot, bool first) {
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    TN s = 0;
-    for (int r = 0; r < rows; ++r) s += Y[(size_t)r * ldy + b];
-    slot[b] = first ? s : slot[b] + s;
-  }
-}
-
-template <typename TN>
 __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64_t nw, int WB,
                                                       const TN* __restrict__ P, ParamLayout pl,
                                                       const TN* __restrict__ xval, const TN* __restrict__ hval,
                                                       const TN* __restrict__ filt, const double* __restrict__ phi,
                                                       const double* __restrict__ ginv, const double* __restrict__ wdet,
                                                       const double* __restrict__ ct_logabs, TN* __restrict__ ctw,
-                                                      TN* __restrict__ gslot, int64_t n_params) {
+                                                      TN* __restrict__ gslot, int64_t n_params,
+                                                      const double* __restrict__ ctfpart, int n_chunks,
+                                                      const TN* __restrict__ cthv, const TN* __restrict__ ctkc,
+                                                      const TN* __restrict__ ctec) {
   extern __shared__ __align__(16) char smem[];
   const int N = d.N, DX = d.DX, DZ = d.DZ, M = d.M, L = d.L, NU = d.n_up;
   const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDM = ld_pad<TN>((M + 15) & ~15);
@@ -158,7 +92,17 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         for (int k = 0; k < n; ++k) CF[row * LDM + dets[p * n + k]] += (TN)(wp * G[ii * n + k]);
       }
       const double* ph = phi + (w * N + i) * M * 7;
-      for (int mu = 0; mu < M; ++mu) CF[row * LDM + mu] *= (TN)(ph[mu * 7]) * cw[wl];
+      if (ctfpart) {
+        // full adjoint: the determinant part supplies the cotangent of f
+        // (its ln|psi| share included), summed over the coordinate chunks
+        for (int mu = 0; mu < M; ++mu) {
+          double v = 0.0;
+          for (int c = 0; c < n_chunks; ++c) v += ctfpart[((w * n_chunks + c) * N + i) * M + mu];
+          CF[row * LDM + mu] = (TN)v;
+        }
+      } else {
+        for (int mu = 0; mu < M; ++mu) CF[row * LDM + mu] *= (TN)(ph[mu * 7]) * cw[wl];
+      }
     }
     __syncthreads();
     // ---- Jastrow head (per walker): J = eta(sum_i x_i) ----
@@ -190,7 +134,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         const int r = q / DX, x = q % DX;
         U2[r * LDX + x] += P[pl.eb2 + x];
         // d/d u2 = cJ * W3[x] * ssp'(u2)
-        C2[r * LDX + x] = cw[r] * P[pl.eW3 + x] * sig(U2[r * LDX + x]);
+        const TN u2 = U2[r * LDX + x];
+        TN c2 = cw[r] * P[pl.eW3 + x] * sig(u2);
+        if (ctec) {  // tangent-pass cotangents of ssp'(u2), ssp''(u2)
+          const TN* ce = ctec + ((w0 + r) * 2 + 1) * 2 * DX;
+          c2 += ce[x] * ssp2(u2) + ce[DX + x] * ssp3(u2);
+        }
+        C2[r * LDX + x] = c2;
       }
       __syncthreads();
       // dW3, db3
@@ -210,7 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
       __syncthreads();
       for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
         const int r = q / DX, x = q % DX;
-        C1[r * LDX + x] *= sig(U1[r * LDX + x]);
+        const TN u1 = U1[r * LDX + x];
+        TN c1 = C1[r * LDX + x] * sig(u1);
+        if (ctec) {
+          const TN* ce = ctec + ((w0 + r) * 2 + 0) * 2 * DX;
+          c1 += ce[x] * ssp2(u1) + ce[DX + x] * ssp3(u1);
+        }
+        C1[r * LDX + x] = c1;
       }
       __syncthreads();
       outer_mfma<TN, false>(Sv, LDX, DX, C1, LDX, DX, nwb, slot + pl.eW1, first);
@@ -243,7 +199,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
       const int r = q / DX, x = q % DX;
       TN s = 0;
       for (int mu = 0; mu < M; ++mu) s += CF[r * LDM + mu] * P[pl.kW3 + x * M + mu];
-      B[r * LDX + x] = s * sig(Cb[r * LDX + x]);  // d/d u2
+      const TN u2 = Cb[r * LDX + x];
+      TN c2 = s * sig(u2);  // d/d u2
+      if (ctkc) {
+        const int64_t wl = w0 + r / N;
+        const TN* ck = ctkc + (wl * 2 + 1) * 2 * N * DX + (r % N) * DX + x;
+        c2 += ck[0] * ssp2(u2) + ck[N * DX] * ssp3(u2);
+      }
+      B[r * LDX + x] = c2;
     }
     __syncthreads();
     outer_mfma<TN, true>(A, LDX, DX, B, LDX, DX, R, slot + pl.kW2, first);
@@ -252,7 +215,14 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
     __syncthreads();
     for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
       const int r = q / DX, x = q % DX;
-      Cb[r * LDX + x] *= sig(A[r * LDX + x]);  // d/d u1
+      const TN u1 = A[r * LDX + x];
+      TN c1 = Cb[r * LDX + x] * sig(u1);  // d/d u1
+      if (ctkc) {
+        const int64_t wl = w0 + r / N;
+        const TN* ck = ctkc + (wl * 2 + 0) * 2 * N * DX + (r % N) * DX + x;
+        c1 += ck[0] * ssp2(u1) + ck[N * DX] * ssp3(u1);
+      }
+      Cb[r * LDX + x] = c1;
     }
     __syncthreads();
     outer_mfma<TN, false>(X, LDX, DX, Cb, LDX, DX, R, slot + pl.kW1, first);
@@ -266,7 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         X[(q / DX) * LDX + q % DX] = xval[((w0 + q / (N * DX)) * (L + 1) + n) * N * DX + q % (N * DX)];
       for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
         H[(q / DZ) * LDZ + q % DZ] = hval[((w0 + q / (N * DZ)) * L + n) * N * DZ + q % (N * DZ)];
-        CH[(q / DZ) * LDZ + q % DZ] = 0;
+        // the tangent pass's cotangent of the h values seeds the h adjoint
+        CH[(q / DZ) * LDZ + q % DZ] = cthv ? cthv[((w0 + q / (N * DZ)) * L + n) * N * DZ + q % (N * DZ)] : TN(0);
       }
       __syncthreads();
       for (int ch = 0; ch < 3; ++ch) {
@@ -349,12 +320,24 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
   }
 }
 
-template <typename TN>
+// JETS: the cotangents also reach the radial derivatives (w'/d and w'') of
+// the filter outputs (full adjoint).  With the jets of the hidden layer
+//   u = e W1 + b1, ud = (e'/d) W1, u2 = e'' W1,
+//   a0 = ssp(u), a1 = s ud, a2 = s u2 + s' (d ud)^2   (s = ssp'(u), s' = ssp''(u))
+//   w = a0 W2 + b2, w'/d = a1 W2, w'' = a2 W2
+// the reverse is
+//   ct a_k = ct w_k W2^T,  dW2 += sum_k a_k^T ct w_k,  db2 += ct w
+//   ct u  = ct a0 s + ct a1 s' ud + ct a2 (s' u2 + s'' (d ud)^2)
+//   ct ud = ct a1 s + 2 ct a2 s' d (d ud),   ct u2 = ct a2 s
+//   dW1 += e^T ct u + (e'/d)^T ct ud + e''^T ct u2,  db1 += ct u.
+template <typename TN, bool JETS>
 __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, int64_t nw, const double* __restrict__ r,
                                                          const TN* __restrict__ P, ParamLayout pl,
-                                                         const TN* __restrict__ ctw, TN* __restrict__ fslot,
-                                                         int n_same) {
+                                                         const TN* __restrict__ ctw, const TN* __restrict__ ctww,
+                                                         const TN* __restrict__ ctwd, const TN* __restrict__ ctw2,
+                                                         TN* __restrict__ fslot, int n_same) {
   extern __shared__ __align__(16) char smem[];
+  constexpr int NJ = JETS ? 3 : 1;
   const int layer = blockIdx.y / 3, ch = blockIdx.y % 3;
   const int K = d.K, DZ = d.DZ, L = d.L;
   const int LDK = ld_pad<TN>(K), LDZ = ld_pad<TN>(DZ);
@@ -364,15 +347,16 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
   const int np = p_hi - p_lo;
   const int64_t nrows = nw * np;
   double* dd = reinterpret_cast<double*>(smem);  // [PT]
-  TN* E = reinterpret_cast<TN*>(dd + PT);        // [PT][LDK] features
-  TN* U = E + PT * LDK;                          // [PT][LDZ] pre-activation of the hidden layer
-  TN* CW = U + PT * LDZ;                         // [PT][LDZ] d/d w
-  TN* CU = CW + PT * LDZ;                        // [PT][LDZ] d/d u
+  TN* E = reinterpret_cast<TN*>(dd + PT);        // [NJ][PT][LDK] feature jets
+  TN* U = E + NJ * PT * LDK;                     // [NJ][PT][LDZ] hidden jets, then activations
+  TN* CW = U + NJ * PT * LDZ;                    // [NJ][PT][LDZ] d/d (w, w'/d, w'')
+  TN* CU = CW + NJ * PT * LDZ;                   // [NJ][PT][LDZ] d/d activations, then d/d hidden jets
   const ParamLayout::Layer& Lp = pl.layer[layer];
   const int fsz = K * DZ + DZ + DZ * DZ + DZ;
-  // weight gradients dW1 = E^T CU and dW2 = ssp(U)^T CW on the matrix cores:
-  // every wavefront keeps its 16 x 16 output tiles in registers across all
-  // row tiles; the reduction runs over the kFiltRows = 32 rows of a tile.
+  // weight gradients dW1 = sum_k E_k^T CU_k and dW2 = sum_k U_k^T CW_k on
+  // the matrix cores: every wavefront keeps its 16 x 16 output tiles in
+  // registers across all row tiles; the reduction runs over the kFiltRows =
+  // 32 rows of a tile.
   typedef typename MfmaTile<TN>::acc_t acc_t;
   constexpr int kMaxT = 8;  // tiles per wavefront: (K/16 + DZ/16) * DZ/16 <= 32
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -411,64 +395,102 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
     __syncthreads();
     for (int q = threadIdx.x; q < PT * K; q += blockDim.x) {
       const int row = q / K, k = q % K;
-      TN e = 0;
+      TN e0 = 0, e1 = 0, e2 = 0;
       if (row < rows) {
-        const double dv = dd[row], dm = dv - t.feat_mu[k];
-        e = (TN)(dv * dv * exp(-dv - dm * dm * t.feat_sig2inv[k]));
+        const double dv = dd[row], dm = dv - t.feat_mu[k], sg = t.feat_sig2inv[k];
+        const double eg = exp(-dv - dm * dm * sg);
+        e0 = (TN)(dv * dv * eg);
+        if (JETS) {
+          const double g1 = -1.0 - 2.0 * dm * sg, g2 = -2.0 * sg;
+          e1 = (TN)((2.0 + dv * g1) * eg);                                  // e'/d
+          e2 = (TN)((2.0 + 4.0 * dv * g1 + dv * dv * (g1 * g1 + g2)) * eg);  // e''
+        }
       }
-      E[row * LDK + k] = e;
+      E[row * LDK + k] = e0;
+      if (JETS) {
+        E[(PT + row) * LDK + k] = e1;
+        E[(2 * PT + row) * LDK + k] = e2;
+      }
     }
     for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) {
       const int row = q / DZ, z = q % DZ;
-      TN v = 0;
+      TN v0 = 0, v1 = 0, v2 = 0;
       if (row < rows) {
         const int64_t gq = row0 + row, w = gq / np;
         const int p = p_lo + (int)(gq % np);
-        v = ctw[((w * L + layer) * d.n_pairs + p) * DZ + z];
+        const int64_t o = ((w * L + layer) * d.n_pairs + p) * DZ + z;
+        v0 = ctw[o];
+        if (JETS) {
+          if (p < d.n_ee) v0 += ctww[((w * L + layer) * d.n_ee + p) * DZ + z];
+          v1 = ctwd[o];
+          v2 = ctw2[o];
+        }
       }
-      CW[row * LDZ + z] = v;
+      CW[row * LDZ + z] = v0;
+      if (JETS) {
+        CW[(PT + row) * LDZ + z] = v1;
+        CW[(2 * PT + row) * LDZ + z] = v2;
+      }
     }
     __syncthreads();
-    gemm_mfma<TN>(E, LDK, PT, K, P + Lp.w1W[ch], DZ, U, LDZ, false, false);
-    __syncthreads();
-    for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) U[(q / DZ) * LDZ + q % DZ] += P[Lp.w1b[ch] + q % DZ];
-    __syncthreads();
-    gemm_mfma_wt<TN>(CW, LDZ, PT, DZ, P + Lp.w2W[ch], DZ, CU, LDZ, false);
+    for (int jet = 0; jet < NJ; ++jet) {
+      gemm_mfma<TN>(E + jet * PT * LDK, LDK, PT, K, P + Lp.w1W[ch], DZ, U + jet * PT * LDZ, LDZ, false, false);
+      gemm_mfma_wt<TN>(CW + jet * PT * LDZ, LDZ, PT, DZ, P + Lp.w2W[ch], DZ, CU + jet * PT * LDZ, LDZ, false);
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < PT * DZ; q += blockDim.x) {
       const int row = q / DZ, z = q % DZ;
-      const TN u = U[row * LDZ + z];
-      CU[row * LDZ + z] = row < rows ? CU[row * LDZ + z] * sig(u) : TN(0);
-      U[row * LDZ + z] = row < rows ? ssp(u) : TN(0);  // hidden activation (zero on padding rows)
+      const bool ok = row < rows;
+      TN* u0 = U + row * LDZ + z;
+      TN* c0 = CU + row * LDZ + z;
+      const TN u = u0[0] + P[Lp.w1b[ch] + z];
+      const TN s = sig(u);
+      if (!JETS) {
+        c0[0] = ok ? c0[0] * s : TN(0);
+        u0[0] = ok ? ssp(u) : TN(0);  // hidden activation (zero on padding rows)
+      } else {
+        const TN s1 = ssp2(u), s2 = ssp3(u), dv = (TN)dd[row];
+        const TN ud = u0[PT * LDZ], u2 = u0[2 * PT * LDZ], up = dv * ud;
+        const TN ca0 = c0[0], ca1 = c0[PT * LDZ], ca2 = c0[2 * PT * LDZ];
+        c0[0] = ok ? ca0 * s + ca1 * s1 * ud + ca2 * (s1 * u2 + s2 * up * up) : TN(0);
+        c0[PT * LDZ] = ok ? ca1 * s + TN(2) * ca2 * s1 * dv * up : TN(0);
+        c0[2 * PT * LDZ] = ok ? ca2 * s : TN(0);
+        u0[0] = ok ? ssp(u) : TN(0);
+        u0[PT * LDZ] = ok ? s * ud : TN(0);
+        u0[2 * PT * LDZ] = ok ? s * u2 + s1 * up * up : TN(0);
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kMaxT; ++k) {
       const int tt = wv + k * (kThreads / 64);
       if (tt < nt) {
-        const TN* X;
-        const TN* Y;
-        int ldx2, a0, b0;
-        if (tt < nt1) {
-          X = E;
-          ldx2 = LDK;
-          Y = CU;
-          a0 = (tt / nz) * 16;
-          b0 = (tt % nz) * 16;
-        } else {
-          X = U;
-          ldx2 = LDZ;
-          Y = CW;
-          a0 = ((tt - nt1) / nz) * 16;
-          b0 = ((tt - nt1) % nz) * 16;
-        }
-        TN af[8], bf[8];
 #pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) {
-          af[s2] = X[(g * 8 + s2) * ldx2 + a0 + c16];
-          bf[s2] = Y[(g * 8 + s2) * LDZ + b0 + c16];
+        for (int jet = 0; jet < NJ; ++jet) {
+          const TN* X;
+          const TN* Y;
+          int ldx2, a0, b0;
+          if (tt < nt1) {
+            X = E + jet * PT * LDK;
+            ldx2 = LDK;
+            Y = CU + jet * PT * LDZ;
+            a0 = (tt / nz) * 16;
+            b0 = (tt % nz) * 16;
+          } else {
+            X = U + jet * PT * LDZ;
+            ldx2 = LDZ;
+            Y = CW + jet * PT * LDZ;
+            a0 = ((tt - nt1) / nz) * 16;
+            b0 = ((tt - nt1) % nz) * 16;
+          }
+          TN af[8], bf[8];
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2) {
+            af[s2] = X[(g * 8 + s2) * ldx2 + a0 + c16];
+            bf[s2] = Y[(g * 8 + s2) * LDZ + b0 + c16];
+          }
+          accs[k] = MfmaChain<TN, 8>::run(af, bf, accs[k], false);
         }
-        accs[k] = MfmaChain<TN, 8>::run(af, bf, accs[k], false);
       }
     }
     if (threadIdx.x < DZ) {
@@ -501,7 +523,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
 template <typename TN>
 __global__ __launch_bounds__(kThreads) void k_bwd_reduce(Dims d, ParamLayout pl, int64_t n_params, int n_net,
                                                          const TN* __restrict__ gslot, int n_filt,
-                                                         const TN* __restrict__ fslot, double* __restrict__ grad) {
+                                                         const TN* __restrict__ fslot, int n_tan,
+                                                         const TN* __restrict__ tslot, double* __restrict__ grad) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_params) return;
   const int fsz = d.K * d.DZ + d.DZ + d.DZ * d.DZ + d.DZ;
@@ -518,6 +541,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reduce(Dims d, ParamLayout pl,
   }
   double s = 0.0;
   for (int b = 0; b < n_net; ++b) s += (double)gslot[(size_t)b * n_params + q];
+  for (int b = 0; b < n_tan; ++b) s += (double)tslot[(size_t)b * n_params + q];
   grad[q] += s;
 }
 
@@ -562,7 +586,7 @@ bool backward_supported(const pn_ctx* c, bool fp32) {
 
 template <typename TN>
 static void run_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, const double* ct,
-                         char* ws, const WsLayout& L, double* grad) {
+                         char* ws, const WsLayout& L, double* grad, bool full) {
   const Dims& d = c->d;
   const int64_t np = c->pl.total;
   TN* gslot = reinterpret_cast<TN*>(ws + L.gpart);
@@ -579,25 +603,45 @@ static void run_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const doubl
                      reinterpret_cast<const TN*>(ws + L.xval), reinterpret_cast<const TN*>(ws + L.hval),
                      reinterpret_cast<const TN*>(ws + L.filt), reinterpret_cast<const double*>(ws + L.phi),
                      reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet), ct,
-                     ctw, gslot, np);
+                     ctw, gslot, np, full ? reinterpret_cast<const double*>(ws + L.ctfpart) : nullptr, L.n_chunks,
+                     full ? reinterpret_cast<const TN*>(ws + L.cthv) : nullptr,
+                     full ? reinterpret_cast<const TN*>(ws + L.ctkc) : nullptr,
+                     full ? reinterpret_cast<const TN*>(ws + L.ctec) : nullptr);
   const int n_same = d.n_up * (d.n_up - 1) / 2 + d.n_dn * (d.n_dn - 1) / 2;
   const int64_t max_np = std::max<int64_t>(std::max(n_same, d.n_ee - n_same), (int64_t)d.N * d.NN);
   const int nb_f = (int)std::min<int64_t>((nw * max_np + kFiltRows - 1) / kFiltRows, kSlotsFilter);
+  const int nj = full ? 3 : 1;
   const size_t lds_f = kFiltRows * sizeof(double) +
-                       (size_t)kFiltRows * (ld_pad<TN>(d.K) + 3 * ld_pad<TN>(d.DZ)) * sizeof(TN);
-  hipLaunchKernelGGL(k_bwd_filter<TN>, dim3(nb_f, d.L * 3), dim3(kThreads), lds_f, s, d, c->t, nw, r, P, c->pl, ctw,
-                     fslot, n_same);
+                       (size_t)nj * kFiltRows * (ld_pad<TN>(d.K) + 3 * ld_pad<TN>(d.DZ)) * sizeof(TN);
+  auto filt_kernel = full ? &k_bwd_filter<TN, true> : &k_bwd_filter<TN, false>;
+  if (lds_f > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(filt_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_f);
+  hipLaunchKernelGGL(filt_kernel, dim3(nb_f, d.L * 3), dim3(kThreads), lds_f, s, d, c->t, nw, r, P, c->pl, ctw,
+                     full ? reinterpret_cast<const TN*>(ws + L.ctww) : nullptr,
+                     full ? reinterpret_cast<const TN*>(ws + L.ctwd) : nullptr,
+                     full ? reinterpret_cast<const TN*>(ws + L.ctw2) : nullptr, fslot, n_same);
+  const int n_tan = full ? (int)std::min<int64_t>(nw, kSlotsTanAdj) : 0;
   hipLaunchKernelGGL(k_bwd_reduce<TN>, dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d,
-                     c->pl, np, nb_net, gslot, nb_f, fslot, grad);
+                     c->pl, np, nb_net, gslot, nb_f, fslot, n_tan, full ? reinterpret_cast<const TN*>(ws + L.tslot) : nullptr,
+                     grad);
 }
 
 void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32, bool bf16,
-                     const double* ct, char* ws, const WsLayout& L, double* grad_params) {
+                     const double* ct, char* ws, const WsLayout& L, double* grad_params, bool full) {
   (void)bf16;
   if (fp32)
-    run_backward<float>(c, s, nw, r, static_cast<const float*>(P), ct, ws, L, grad_params);
+    run_backward<float>(c, s, nw, r, static_cast<const float*>(P), ct, ws, L, grad_params, full);
   else
-    run_backward<double>(c, s, nw, r, static_cast<const double*>(P), ct, ws, L, grad_params);
+    run_backward<double>(c, s, nw, r, static_cast<const double*>(P), ct, ws, L, grad_params, full);
+}
+
+size_t backward_filter_lds_bytes(const Dims& d, bool fp32, bool full) {
+  const int nj = full ? 3 : 1;
+  const size_t tn = fp32 ? sizeof(float) : sizeof(double);
+  const size_t ldk = fp32 ? ld_pad<float>(d.K) : ld_pad<double>(d.K);
+  const size_t ldz = fp32 ? ld_pad<float>(d.DZ) : ld_pad<double>(d.DZ);
+  return kFiltRows * sizeof(double) + (size_t)nj * kFiltRows * (ldk + 3 * ldz) * tn;
 }
 
 }  // namespace pn

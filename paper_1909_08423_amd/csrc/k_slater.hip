@@ -208,7 +208,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
                                                              const double* __restrict__ jtan,
                                                              const double* __restrict__ ginv,
                                                              const double* __restrict__ wdet,
-                                                             double* __restrict__ grad, double* __restrict__ partial) {
+                                                             double* __restrict__ grad, double* __restrict__ partial,
+                                                             double* __restrict__ detres) {
   extern __shared__ __align__(16) char smem[];
   const int64_t task = blockIdx.x;
   const int64_t w = task / n_chunks;
@@ -314,6 +315,16 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
     wave_sync();
   }
   __syncthreads();
+  // per-determinant results for the adjoint pass: [P][2][T+1] per (walker,
+  // chunk): d_a ln det for the chunk's coordinates, then the chunk's part of
+  // the Laplacian of ln det at index T
+  if (detres) {
+    double* dr = detres + (size_t)task * P * 2 * (T + 1);
+    for (int q = threadIdx.x; q < P * 2 * (T + 1); q += blockDim.x) {
+      const int ps = q / (T + 1), col = q % (T + 1);
+      dr[q] = col < Tc ? gres[(size_t)ps * T + col] : (col == T ? dres[ps] : 0.0);
+    }
+  }
   // determinant sum per coordinate, then gamma and J
   const double* g = geo + w * kGeoStride(N);
   const double* jt = jtan + (w * n_chunks + chunk) * (T + 1);
@@ -384,7 +395,7 @@ size_t slater_tangent_lds_bytes(const Dims& d, int T) {
 }
 
 void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws, const WsLayout& L,
-                           double* grad) {
+                           double* grad, double* detres) {
   const Dims& d = c->d;
   (void)r;
   size_t lds = slater_tangent_lds_bytes(d, L.T);
@@ -398,7 +409,7 @@ void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
                        reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
                        reinterpret_cast<const double*>(ws + L.ftan), reinterpret_cast<const double*>(ws + L.jtan),
                        reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet),
-                       grad, reinterpret_cast<double*>(ws + L.partial));
+                       grad, reinterpret_cast<double*>(ws + L.partial), detres);
   };
   if (NM <= 8)
     go(&k_slater_tangent<8>);

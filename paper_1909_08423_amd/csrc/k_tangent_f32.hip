@@ -3,5 +3,5 @@
 
 namespace pn {
 template void launch_net_tangent<float>(const pn_ctx*, hipStream_t, int64_t, const double*, const float*, char*,
-                                        const WsLayout&, bool);
+                                        const WsLayout&, bool, float*);
 }  // namespace pn

@@ -24,5 +24,5 @@ size_t tangent_lds_bytes(const Dims& d, int T, bool stage) {
 template size_t tangent_lds_bytes<double>(const Dims&, int, bool);
 template size_t tangent_lds_bytes<float>(const Dims&, int, bool);
 template void launch_net_tangent<double>(const pn_ctx*, hipStream_t, int64_t, const double*, const double*, char*,
-                                         const WsLayout&, bool);
+                                         const WsLayout&, bool, double*);
 }  // namespace pn

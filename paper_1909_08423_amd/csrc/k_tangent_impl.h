@@ -47,7 +47,8 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
                                                            ParamLayout pl, const TN* __restrict__ filt,
                                                            const TN* __restrict__ hval, const TN* __restrict__ kcoef,
                                                            const TN* __restrict__ ecoef, double* __restrict__ ftan,
-                                                           double* __restrict__ jtan, bool bf16) {
+                                                           double* __restrict__ jtan, TN* __restrict__ xsave,
+                                                           bool bf16) {
   constexpr int T = C - 1, LC = T;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
@@ -114,6 +115,11 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
     const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
     const TN* hv = hval + (w * d.L + n) * N * DZ;
     for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) hvs[q] = hv[q];
+    // the adjoint pass re-reads the layer inputs x^(n), n >= 1 (x^(0) has no tangents)
+    if (xsave && n > 0) {
+      TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (n - 1)) * R * DX;
+      for (int q = threadIdx.x; q < R * DX; q += blockDim.x) xs[q] = XT[(q / DX) * LDX + q % DX];
+    }
     if constexpr (STAGE) {
       for (int q = threadIdx.x; q < d.n_ee * DZ; q += blockDim.x) wvs[q] = fv[q];
       for (int q = threadIdx.x; q < NCE * NP * DZ; q += blockDim.x) {
@@ -260,6 +266,10 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
                   true, bf16);
     __syncthreads();
   }
+  if (xsave) {
+    TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (d.L - 1)) * R * DX;
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) xs[q] = XT[(q / DX) * LDX + q % DX];
+  }
   // ---- Jastrow head on sum_i x_i, rows = columns ----
   TN* S0 = ES;             // [C][LDX]
   TN* S1 = ES + C * LDX;   // [C][LDX]
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
 
 template <typename TN, int C, bool STAGE>
 void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
-              bool bf16) {
+              bool bf16, TN* xsave) {
   const int64_t nb = nw * L.n_chunks;
   if (L.lds_tangent > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_net_tangent<TN, C, STAGE>),
@@ -345,24 +355,24 @@ void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const
                      c->t, nw, L.n_chunks, r, P, c->pl, reinterpret_cast<const TN*>(ws + L.filt),
                      reinterpret_cast<const TN*>(ws + L.hval), reinterpret_cast<const TN*>(ws + L.kcoef),
                      reinterpret_cast<const TN*>(ws + L.ecoef), reinterpret_cast<double*>(ws + L.ftan),
-                     reinterpret_cast<double*>(ws + L.jtan), bf16);
+                     reinterpret_cast<double*>(ws + L.jtan), xsave, bf16);
 }
 
 template <typename TN, bool STAGE>
 void launch_t(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
-              bool bf16) {
+              bool bf16, TN* xsave) {
   switch (L.T + 1) {
-    case 2: launch_c<TN, 2, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 3: launch_c<TN, 3, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 4: launch_c<TN, 4, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 5: launch_c<TN, 5, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 6: launch_c<TN, 6, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 7: launch_c<TN, 7, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 9: launch_c<TN, 9, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 10: launch_c<TN, 10, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 11: launch_c<TN, 11, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 13: launch_c<TN, 13, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
-    case 16: launch_c<TN, 16, STAGE>(c, s, nw, r, P, ws, L, bf16); break;
+    case 2: launch_c<TN, 2, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 3: launch_c<TN, 3, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 4: launch_c<TN, 4, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 5: launch_c<TN, 5, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 6: launch_c<TN, 6, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 7: launch_c<TN, 7, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 9: launch_c<TN, 9, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 10: launch_c<TN, 10, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 11: launch_c<TN, 11, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 13: launch_c<TN, 13, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
+    case 16: launch_c<TN, 16, STAGE>(c, s, nw, r, P, ws, L, bf16, xsave); break;
     default: break;  // the planner only picks supported chunk sizes
   }
 }
@@ -371,11 +381,11 @@ void launch_t(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const
 
 template <typename TN>
 void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
-                        const WsLayout& L, bool bf16) {
+                        const WsLayout& L, bool bf16, TN* xsave) {
   if (L.stage_filters)
-    launch_t<TN, true>(c, s, nw, r, P, ws, L, bf16);
+    launch_t<TN, true>(c, s, nw, r, P, ws, L, bf16, xsave);
   else
-    launch_t<TN, false>(c, s, nw, r, P, ws, L, bf16);
+    launch_t<TN, false>(c, s, nw, r, P, ws, L, bf16, xsave);
 }
 
 }  // namespace pn

@@ -1,4 +1,4 @@
-// Parameter conversion to the network precision.
+// Parameter conversion to the network precision; zero fill.
 #include "pn_internal.h"
 
 namespace pn {
@@ -8,7 +8,17 @@ __global__ __launch_bounds__(kThreads) void k_convert(int64_t n, const double* _
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
 }
+__global__ __launch_bounds__(kThreads) void k_zero(int64_t n, double* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = 0.0;
+}
 }  // namespace
+
+// zero fill by a kernel (stays a kernel node if the caller captures the stream)
+void launch_fill0(hipStream_t s, int64_t n, double* dst) {
+  int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 1024));
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)nb), dim3(kThreads), 0, s, n, dst);
+}
 
 void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst) {
   int64_t nb = std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);

@@ -279,7 +279,7 @@ pn_status pn_vmc_step(const pn_ctx* c, hipStream_t s, const pn_vmc_job* job, pn_
   const int64_t np = c->pl.total;
   const unsigned nbp = (unsigned)std::min<int64_t>((np + kThreads - 1) / kThreads, 2048);
   hipLaunchKernelGGL(k_fill0, dim3(nbp), dim3(kThreads), 0, s, np, gp);
-  st = pn_eval_backward(c, s, B, job->r, job->params, prec, ct, gp, wse, wse_bytes);
+  st = pn_eval_backward(c, s, B, job->r, job->params, prec, ct, nullptr, nullptr, nullptr, gp, wse, wse_bytes);
   if (st != PN_OK) return st;
   // 7: AdamW
   hipLaunchKernelGGL(k_adamw, dim3(nbp), dim3(kThreads), 0, s, np, job->params, gp, job->adam_m, job->adam_v,

@@ -20,7 +20,13 @@ template <typename TN>
 size_t filter_lds_bytes(const Dims& d, int PT);
 bool tangent_chunk_supported(int T);
 void launch_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const void* P, bool fp32,
-                     bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params);
+                     bool bf16, const double* ct, char* ws, const WsLayout& L, double* grad_params, bool full);
+size_t backward_filter_lds_bytes(const Dims& d, bool fp32, bool full);
+size_t adj_slater_lds_bytes(const Dims& d, int T);
+template <typename TN>
+size_t tangent_adj_arena_elems(const Dims& d, int T);
+template <typename TN>
+size_t tangent_adj_lds_bytes(const Dims& d, int T, bool global_arena);
 size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32);
 bool backward_supported(const pn_ctx* c, bool fp32);
 
@@ -118,11 +124,43 @@ bool solve3(double M[3][3], double b[3], double x[3]) {
 }  // namespace
 
 // Workspace plan for `nw` walkers; net_bytes = sizeof of the network type.
-WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
+// mode 0: forward; 1: forward + value-path adjoint; 2: also the full
+// adjoint (cotangents on the gradient, Laplacian and E_loc).
+enum { kPlanForward = 0, kPlanValueAdjoint = 1, kPlanFullAdjoint = 2 };
+
+// chunk size of the full adjoint: the largest T in 1..6 whose tangent-adjoint
+// block keeps its row buffers in LDS; when none fits, the row buffers go to a
+// per-block global arena and T is the largest whose small tables fit
+void plan_full_adjoint(const Dims& d, bool fp64, WsLayout& L) {
+  auto lds = [&](int T, bool ga) {
+    return fp64 ? tangent_adj_lds_bytes<double>(d, T, ga) : tangent_adj_lds_bytes<float>(d, T, ga);
+  };
+  const int ncoord = 3 * d.N;
+  L.T = 0;
+  for (int pass = 0; pass < 2 && L.T == 0; ++pass) {
+    const bool ga = pass == 1;
+    for (int T = std::min(6, ncoord); T >= 1; --T) {
+      if (!tangent_chunk_supported(T)) continue;
+      if (lds(T, ga) <= kLdsMax && adj_slater_lds_bytes(d, T) <= kLdsMax) {
+        L.T = T;
+        L.tadj_global = ga;
+        break;
+      }
+    }
+  }
+  if (L.T == 0) L.T = 1;  // reported unsupported by the caller (LDS over the limit)
+  L.lds_tadj = lds(L.T, L.tadj_global);
+  L.lds_adjdet = adj_slater_lds_bytes(d, L.T);
+  L.tadj_arena = fp64 ? tangent_adj_arena_elems<double>(d, L.T) : tangent_adj_arena_elems<float>(d, L.T);
+}
+
+WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
   const Dims& d = c->d;
   const bool fp64 = prec == PN_PREC_FP64;
+  const bool backward = mode >= kPlanValueAdjoint, full = mode == kPlanFullAdjoint;
   const size_t tn = fp64 ? sizeof(double) : sizeof(float);
   WsLayout L{};
+  L.full = full;
   // chunking of the 3N coordinates for the tangent pass: the largest chunk
   // whose block fits the LDS budget, preferring the form that stages the
   // filter tables in LDS
@@ -143,6 +181,11 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
         break;
       }
     }
+  }
+  if (full) {
+    // the forward tangent pass runs with the adjoint's chunking
+    plan_full_adjoint(d, fp64, L);
+    L.stage_filters = lds_of(L.T, true) <= budget;
   }
   L.n_chunks = (ncoord + L.T - 1) / L.T;
   L.lds_tangent = lds_of(L.T, L.stage_filters);
@@ -172,6 +215,14 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
     b += (size_t)L.n_chunks * N * Tp * M * 8 + (size_t)L.n_chunks * Tp * 8 + (size_t)L.n_chunks * 2 * 8;
     b += (size_t)N * 3 * 8;
     if (with_bwd) b += (size_t)(d.L + 1) * N * d.DX * tn;
+    if (full) {
+      const size_t nc = L.n_chunks, N3 = 3 * N;
+      b += nc * d.L * N * Tp * d.DX * tn;                     // xsave
+      b += nc * P * 2 * Tp * 8 + N3 * 8 + (N3 + 2) * 8 + (size_t)P * (N3 + 2) * 8 + 8;
+      b += nc * N * Tp * M * 8 + nc * N * M * 8;              // ctftan, ctfpart
+      b += ((size_t)d.L * N * d.DZ + (size_t)d.L * d.n_ee * d.DZ + 2 * (size_t)d.L * d.n_pairs * d.DZ +
+            4 * (size_t)N * d.DX + 4 * (size_t)d.DX) * tn;
+    }
     return b;
   };
   size_t pw = per_walker(backward);
@@ -207,6 +258,25 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, bool backward) {
   if (backward) {
     L.xval = region((size_t)tile * (d.L + 1) * N * d.DX * tn);
     L.gpart = region(backward_scratch_bytes(c, tile, !fp64));
+  }
+  if (full) {
+    const size_t nc = L.n_chunks, N3 = 3 * N;
+    L.xsave = region((size_t)tile * nc * d.L * N * Tp * d.DX * tn);
+    L.detres = region((size_t)tile * nc * P * 2 * Tp * 8);
+    L.gradf = region((size_t)tile * N3 * 8);
+    L.ctc = region((size_t)tile * (N3 + 2) * 8);
+    L.ctdet = region((size_t)tile * P * (N3 + 2) * 8);
+    L.ctftan = region((size_t)tile * nc * N * Tp * M * 8);
+    L.ctfpart = region((size_t)tile * nc * N * M * 8);
+    L.cthv = region((size_t)tile * d.L * N * d.DZ * tn);
+    L.ctww = region((size_t)tile * d.L * d.n_ee * d.DZ * tn);
+    L.ctwd = region((size_t)tile * d.L * d.n_pairs * d.DZ * tn);
+    L.ctw2 = region((size_t)tile * d.L * d.n_pairs * d.DZ * tn);
+    L.ctkc = region((size_t)tile * 4 * N * d.DX * tn);
+    L.ctec = region((size_t)tile * 4 * d.DX * tn);
+    L.ct0 = region((size_t)tile * 8);
+    L.tslot = region(((size_t)kSlotsTanAdj * c->pl.total + (L.tadj_global ? (size_t)kSlotsTanAdj * L.tadj_arena : 0)) *
+                     tn);
   }
   L.total = off;
   return L;
@@ -493,8 +563,14 @@ int64_t pn_param_count(const pn_ctx* c) { return c ? c->pl.total : -1; }
 
 pn_status pn_workspace_bytes(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
   if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
-  WsLayout L = plan(c, nw, prec, true);
-  *bytes = L.total;
+  *bytes = std::max(plan(c, nw, prec, kPlanForward).total, plan(c, nw, prec, kPlanValueAdjoint).total);
+  return PN_OK;
+}
+
+pn_status pn_workspace_bytes_full(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
+  if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  *bytes = std::max(std::max(plan(c, nw, prec, kPlanForward).total, plan(c, nw, prec, kPlanValueAdjoint).total),
+                    plan(c, nw, prec, kPlanFullAdjoint).total);
   return PN_OK;
 }
 
@@ -505,7 +581,7 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
   if (nw == 0) return PN_OK;
   if (!r || !params || !logabs || !sign || !ws) return PN_ERR_INVALID_ARG;
   const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
-  WsLayout L = plan(c, nw, prec, false);
+  WsLayout L = plan(c, nw, prec, kPlanForward);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
   if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
   char* base = static_cast<char*>(ws);
@@ -565,23 +641,28 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
 }
 
 pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
-                           pn_precision prec, const double* ct_logabs, double* grad_params, void* ws,
-                           size_t ws_bytes) {
+                           pn_precision prec, const double* ct_logabs, const double* ct_grad, const double* ct_lap,
+                           const double* ct_eloc, double* grad_params, void* ws, size_t ws_bytes) {
   if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
   if (nw == 0) return PN_OK;
-  if (!r || !params || !ct_logabs || !grad_params || !ws) return PN_ERR_INVALID_ARG;
+  if (!r || !params || !grad_params || !ws) return PN_ERR_INVALID_ARG;
+  const bool full = ct_grad || ct_lap || ct_eloc;
+  if (!full && !ct_logabs) return PN_OK;  // every cotangent is zero
   const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
   if (!backward_supported(c, !fp64)) return PN_ERR_UNSUPPORTED_SHAPE;
-  WsLayout L = plan(c, nw, prec, true);
+  WsLayout L = plan(c, nw, prec, full ? kPlanFullAdjoint : kPlanValueAdjoint);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
+  const Dims& d = c->d;
+  if (full && (L.lds_tadj > kLdsMax || L.lds_adjdet > kLdsMax || L.lds_tangent > kLdsMax ||
+               backward_filter_lds_bytes(d, !fp64, true) > kLdsMax))
+    return PN_ERR_UNSUPPORTED_SHAPE;
   char* base = static_cast<char*>(ws);
   const void* P = params;
   if (!fp64) {
     launch_convert_params(s, c->pl.total, params, reinterpret_cast<float*>(base + L.params_net));
     P = base + L.params_net;
   }
-  const Dims& d = c->d;
-  // the value pass is recomputed here (nothing is kept between calls); its
+  // the forward pass is recomputed here (nothing is kept between calls); its
   // ln|psi| and sign go to scratch
   double* la = reinterpret_cast<double*>(base + L.adj);
   double* sg = la + L.tile;
@@ -597,7 +678,30 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
       launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
     }
     launch_slater_value(c, s, n, base, L, la, sg);
-    launch_backward(c, s, n, rt, P, !fp64, bf16, ct_logabs + w0, base, L, grad_params);
+    const double* ctl = ct_logabs ? ct_logabs + w0 : nullptr;
+    if (full) {
+      // coordinate derivatives with the layer inputs and per-determinant
+      // results kept, then the determinant and network-tangent adjoints
+      if (fp64)
+        launch_net_tangent<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false,
+                                   reinterpret_cast<double*>(base + L.xsave));
+      else
+        launch_net_tangent<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16,
+                                  reinterpret_cast<float*>(base + L.xsave));
+      launch_slater_tangent(c, s, n, rt, base, L, reinterpret_cast<double*>(base + L.gradf),
+                            reinterpret_cast<double*>(base + L.detres));
+      launch_adj_det(c, s, n, L, base, ctl, ct_grad ? ct_grad + w0 * d.N * 3 : nullptr, ct_lap ? ct_lap + w0 : nullptr,
+                     ct_eloc ? ct_eloc + w0 : nullptr);
+      if (fp64)
+        launch_net_tangent_adj<double>(c, s, n, rt, static_cast<const double*>(P), base, L);
+      else
+        launch_net_tangent_adj<float>(c, s, n, rt, static_cast<const float*>(P), base, L);
+      if (!ctl) {
+        launch_fill0(s, n, reinterpret_cast<double*>(base + L.ct0));
+        ctl = reinterpret_cast<const double*>(base + L.ct0);
+      }
+    }
+    launch_backward(c, s, n, rt, P, !fp64, bf16, ctl, base, L, grad_params, full);
   }
   if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
   return PN_OK;

@@ -101,8 +101,31 @@ struct WsLayout {
   size_t xval;         // [tile][L+1][N][DX] activations (backward only)
   size_t adj;          // backward scratch
   size_t gpart;        // [n_blocks][n_params] per-block parameter gradients
+  // full adjoint (cotangents on grad / lap / E_loc)
+  bool full;
+  bool tadj_global;    // tangent-adjoint row buffers in a global arena (else LDS)
+  size_t lds_tadj;     // dynamic LDS of the tangent adjoint
+  size_t lds_adjdet;   // dynamic LDS of the determinant adjoint
+  size_t tadj_arena;   // elements of one block's row buffers
+  size_t xsave;        // [tile][n_chunks][L][N(T+1)][DX] net type: layer inputs of the tangent pass
+  size_t detres;       // [tile][n_chunks][P][2][T+1] per-determinant derivatives
+  size_t gradf;        // [tile][3N] gradient of ln|psi|
+  size_t ctc;          // [tile][3N+2] (ct grad', ct lap', ct ln|psi|)
+  size_t ctdet;        // [tile][P][3N+2] (ct g_pa, ct Delta_p, ct l_p)
+  size_t ctftan;       // [tile][n_chunks][N][T+1][M] ct of f tangents / partial Laplacians
+  size_t ctfpart;      // [tile][n_chunks][N][M] ct of f, per chunk
+  size_t cthv;         // [tile][L][N][DZ]       net type
+  size_t ctww;         // [tile][L][n_ee][DZ]    net type
+  size_t ctwd;         // [tile][L][n_pairs][DZ] net type
+  size_t ctw2;         // [tile][L][n_pairs][DZ] net type
+  size_t ctkc;         // [tile][2][2][N][DX]    net type
+  size_t ctec;         // [tile][2][2][DX]       net type
+  size_t ct0;          // [tile] zeros (absent ln|psi| cotangent)
+  size_t tslot;        // [kSlotsTanAdj][n_params] + global arena, net type
   size_t total;
 };
+
+constexpr int kSlotsTanAdj = 512;  // blocks (and gradient slots) of the tangent adjoint
 
 constexpr int kGeoStride(int N) { return 4 + 6 * N; }  // V, gamma, lap_gamma, pad, N*(grad3, hess3)
 
@@ -162,12 +185,18 @@ void launch_net_value(const pn_ctx* c, hipStream_t s, int64_t nw, const TN* P, c
                       bool bf16);
 template <typename TN>
 void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
-                        const WsLayout& L, bool bf16);
+                        const WsLayout& L, bool bf16, TN* xsave = nullptr);
 void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L,
                          double* logabs, double* sign);
 void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws,
-                           const WsLayout& L, double* grad);
+                           const WsLayout& L, double* grad, double* detres = nullptr);
 void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* grad,
                      double* lap, double* eloc);
 void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst);
+void launch_fill0(hipStream_t s, int64_t n, double* dst);
+void launch_adj_det(const pn_ctx* c, hipStream_t s, int64_t nw, const WsLayout& L, char* ws, const double* ct_logabs,
+                    const double* ct_grad, const double* ct_lap, const double* ct_eloc);
+template <typename TN>
+void launch_net_tangent_adj(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws,
+                            const WsLayout& L);
 }  // namespace pn

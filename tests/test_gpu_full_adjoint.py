@@ -1,0 +1,129 @@
+"""GPU parity of the full parameter adjoint (cotangents on the gradient,
+Laplacian and E_loc of ln|psi|, the Laplacian's second-order terms included)
+against the FP64 oracle, through the C ABI and through the autograd Function.
+
+Oracle gradients are stored fixtures written by
+tests/golden/make_oracle_fixtures.py --full (third-order autograd in the
+oracle, itself pinned by finite differences in theta).  FP64 bar: ||d g|| <=
+1e-8 ||g|| and every component within 1e-7 max|g|.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import GOLDEN, announce
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+
+SETS = {"grad": ("ct_grad",), "lap": ("ct_lap",), "eloc": ("ct_eloc",),
+        "all": ("ct_logabs", "ct_grad", "ct_lap", "ct_eloc")}
+
+
+@pytest.fixture(scope="module")
+def pn():
+    import paper_1909_08423_amd as pn
+    assert torch.cuda.is_available(), "no ROCm device"
+    pn.load_library()
+    return pn
+
+
+def _fixture(idx):
+    return dict(np.load(os.path.join(GOLDEN, f"oracle_full_adjoint_cfg{idx}.npz")))
+
+
+def _call(pn, ctx, fx, th, which, prec, grad_params=None):
+    dev = "cuda"
+    r = torch.tensor(fx["walkers"], dtype=torch.float64, device=dev)
+    kw = {k: torch.tensor(fx[k], dtype=torch.float64, device=dev) for k in SETS[which]}
+    g = ctx.eval_backward(r, th, kw.pop("ct_logabs", None), prec, grad_params=grad_params, **kw)
+    torch.cuda.synchronize()
+    return g
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+@pytest.mark.parametrize("which", ["grad", "lap", "eloc", "all"])
+def test_full_adjoint_fp64_matches_oracle(pn, idx, which):
+    fx = _fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    announce(f"fp64 full adjoint workload {idx} cotangents {which} B={fx['walkers'].shape[0]}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    g0 = torch.full((ctx.param_count,), 0.25, dtype=torch.float64, device="cuda")
+    got = _call(pn, ctx, fx, th, which, pn.PN_PREC_FP64, grad_params=g0.clone()).cpu().numpy() - 0.25
+    ref = fx["g_" + which]
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    comp = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"[fp64 full adjoint cfg{idx} {which}] relative L2 {rel:.3e}, max component {comp:.3e}")
+    assert rel <= 1e-8
+    assert comp <= 1e-7
+
+
+@pytest.mark.parametrize("idx,prec", [(2, "fp32"), (3, "fp32"), (3, "bf16")])
+def test_full_adjoint_mixed_error_statement(pn, idx, prec):
+    fx = _fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    announce(f"{prec} full adjoint workload {idx}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    got = _call(pn, ctx, fx, th, "all", pn._lib.PRECISIONS[prec]).cpu().numpy()
+    ref = fx["g_all"]
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"[{prec} full adjoint cfg{idx}] relative L2 error {rel:.3e}")
+    assert rel < (1e-2 if prec == "fp32" else 0.3)
+
+
+def test_full_adjoint_with_zero_coordinate_cotangents_is_value_adjoint(pn):
+    """Zero cotangents on grad and Laplacian route through the full adjoint
+    (determinant and tangent adjoints) and must reproduce the value-path
+    adjoint of the ln|psi| cotangent."""
+    w = make_config(2, n_walkers=40)
+    announce("full adjoint with zero coordinate cotangents, workload 2, B=40")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ct = torch.tensor(np.random.default_rng(4).standard_normal(40), device="cuda")
+    a = ctx.eval_backward(r, th, ct, pn.PN_PREC_FP64)
+    b = ctx.eval_backward(r, th, ct, pn.PN_PREC_FP64, ct_grad=torch.zeros(40, w.system.n_elec, 3, device="cuda",
+                                                                            dtype=torch.float64),
+                          ct_lap=torch.zeros(40, device="cuda", dtype=torch.float64))
+    torch.cuda.synchronize()
+    assert float(torch.linalg.norm(a - b)) <= 1e-10 * float(torch.linalg.norm(a))
+
+
+def test_full_adjoint_deterministic(pn):
+    w = make_config(3, n_walkers=300)
+    announce("full adjoint determinism, workload 3, B=300")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ce = torch.tensor(np.random.default_rng(5).standard_normal(300), device="cuda")
+    a = ctx.eval_backward(r, th, None, pn.PN_PREC_FP64, ct_eloc=ce)
+    b = ctx.eval_backward(r, th, None, pn.PN_PREC_FP64, ct_eloc=ce)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_autograd_function_matches_c_abi(pn):
+    """paulinet_eval as a torch.autograd.Function: d/d params of a loss built
+    from all five outputs equals pn_eval_backward with the loss's output
+    cotangents (and the oracle's gradient for the same cotangents)."""
+    idx = 2
+    fx = _fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    announce("autograd Function, workload 2")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(fx["walkers"], dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda", requires_grad=True)
+    la, sg, g, lap, el = pn.paulinet_eval(ctx, r, th, pn.PN_PREC_FP64)
+    c = {k: torch.tensor(fx[k], dtype=torch.float64, device="cuda") for k in SETS["all"]}
+    loss = (c["ct_logabs"] * la).sum() + (c["ct_grad"] * g).sum() + (c["ct_lap"] * lap).sum() + \
+        (c["ct_eloc"] * el).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    got = th.grad.cpu().numpy()
+    ref = fx["g_all"]
+    assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
