@@ -186,23 +186,45 @@ def time_vmc_step(pn, ctx, w, prec, steps, warmup, torch):
             "steps": steps, "last_stats": st["stats"].cpu().numpy().tolist()}
 
 
-def run_serving(pn, prec, n_jobs, n_steps, torch):
+def time_full_adjoint(ctx, r, th, prec, steps, warmup, torch):
+    """Full parameter adjoint (cotangent on E_loc: the forward recomputation,
+    the determinant and tangent-pass adjoints and the value-path adjoint)
+    over the benchmark batch."""
+    B = r.shape[0]
+    ce = torch.ones(B, dtype=torch.float64, device="cuda") / B
+    ws = ctx.workspace(B, prec, r.device, full=True)
+    g = torch.zeros(ctx.param_count, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ctx.eval_backward(r, th, None, prec, grad_params=g, ws=ws, ct_eloc=ce)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.eval_backward(r, th, None, prec, grad_params=g, ws=ws, ct_eloc=ce)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"walkers_per_s": B * steps / dt, "ms_per_call": dt / steps * 1e3, "steps": steps,
+            "workspace_GiB": ws.numel() / 2**30}
+
+
+def run_serving(pn, prec, n_jobs, n_steps, torch, mean_gap_s=0.05, budget_gib=64):
     """The serving stream (H-chains and atoms, 2-18 electrons, 1-32
-    determinants, 1024-8192 walkers, Poisson arrivals), shortened to n_jobs
-    jobs of n_steps steps."""
+    determinants, 1024-8192 walkers, Poisson arrivals): n_jobs jobs of
+    n_steps steps, mean inter-arrival mean_gap_s, device-memory budget
+    budget_gib for admission."""
     from paper_1909_08423_amd.serve import GpuBackend, JobSpec, Server, summarize
     from synth import make_serving_jobs
-    jobs = make_serving_jobs(n_jobs=n_jobs, n_steps=n_steps, mean_gap_s=0.05)
+    jobs = make_serving_jobs(n_jobs=n_jobs, n_steps=n_steps, mean_gap_s=mean_gap_s)
     specs = [JobSpec(j.job_id, j.arrival_s, j.n_steps, j.workload.system, j.workload.net, j.workload.params,
                      j.workload.walkers, seed=1000 + j.job_id) for j in jobs]
     be = GpuBackend(prec=prec, n_streams=8)
-    srv = Server(be, mem_budget_bytes=64 << 30, max_active=16)
+    srv = Server(be, mem_budget_bytes=int(budget_gib * 2**30), max_active=16)
     t0 = time.perf_counter()
     recs = srv.run(specs)
     torch.cuda.synchronize()
     out = summarize(recs, time.perf_counter() - t0)
     out.update({"jobs": n_jobs, "steps_per_job": n_steps, "max_concurrency": srv.max_concurrency,
-                "mem_budget_GiB": 64, "electrons": [int(s.walkers.shape[1]) for s in specs],
+                "mean_gap_s": mean_gap_s, "mem_budget_GiB": budget_gib,
+                "max_bytes_in_use_GiB": srv.max_bytes_in_use / 2**30, "electrons": [int(s.walkers.shape[1]) for s in specs],
                 "walkers": [int(s.walkers.shape[0]) for s in specs]})
     return out
 
@@ -219,6 +241,9 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-full-adjoint", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -305,8 +330,13 @@ def main():
     if probe is not None:
         res["copy_probe"] = probe
     res["vmc_step"] = time_vmc_step(pn, ctx, w, P[args.prec], max(3, args.steps // 4), 1, torch)
+    if not args.no_full_adjoint:
+        res["full_adjoint_eloc"] = {
+            args.prec: time_full_adjoint(ctx, r, th, P[args.prec], max(3, args.steps // 4), 1, torch),
+            "fp64": time_full_adjoint(ctx, r, th, P["fp64"], max(3, args.steps // 4), 1, torch)}
     if not args.no_serve:
-        res["serving"] = run_serving(pn, P[args.prec], args.serve_jobs, args.serve_steps, torch)
+        res["serving"] = run_serving(pn, P[args.prec], args.serve_jobs, args.serve_steps, torch, args.serve_gap,
+                                     args.serve_budget_gib)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -122,6 +122,22 @@ void pn_ctx_destroy(pn_ctx* ctx);
  *   kappa: W1[D_x][D_x] b1[D_x] W2[D_x][D_x] b2[D_x] W3[D_x][n_mo] b3[n_mo]. */
 int64_t pn_param_count(const pn_ctx* ctx);
 
+/* One named tensor of the parameter blob: element offset, rank (1 or 2)
+ * and shape (rows, columns; columns 0 for a vector).  Names: "x0", "Y",
+ * "l<n>.w_<c>.W1|b1|W2|b2", "l<n>.h.W|b", "l<n>.g_<c>.W|b" with c in
+ * {same, opp, nuc}, "eta.W1".."eta.b3", "kappa.W1".."kappa.b3". */
+typedef struct {
+  char name[32];
+  int64_t offset;
+  int32_t ndim;
+  int32_t shape[2];
+} pn_param_entry;
+
+/* Fills entries[0 .. cap-1] ([host]) in blob order and sets *n to the total
+ * number of tensors; returns PN_ERR_INVALID_ARG (with *n set) when cap is
+ * too small, so a call with cap = 0 queries the count. */
+pn_status pn_param_layout(const pn_ctx* ctx, pn_param_entry* entries, int32_t cap, int32_t* n);
+
 /* Workspace bytes for a call with n_walkers walkers at the given
  * precision.  Batches larger than the internal walker tile are processed
  * tile by tile, so the size stops growing at the tile. */

@@ -55,6 +55,11 @@ class pn_net_desc(ctypes.Structure):
     ]
 
 
+class pn_param_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("offset", ctypes.c_int64), ("ndim", ctypes.c_int32),
+                ("shape", ctypes.c_int32 * 2)]
+
+
 class pn_vmc_hparams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("sigma", "lr0", "t0", "clip_q", "beta1", "beta2", "eps", "weight_decay")]
@@ -110,6 +115,8 @@ def load_library():
     lib.pn_workspace_bytes.restype = i32
     lib.pn_eval.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.pn_eval.restype = i32
+    lib.pn_param_layout.argtypes = [vp, ctypes.POINTER(pn_param_entry), i32, ctypes.POINTER(i32)]
+    lib.pn_param_layout.restype = i32
     lib.pn_workspace_bytes_full.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pn_workspace_bytes_full.restype = i32
     lib.pn_eval_backward.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
@@ -208,6 +215,14 @@ class PauliNetContext:
     @property
     def param_count(self):
         return int(self._lib.pn_param_count(self._ctx))
+
+    def param_layout(self):
+        """[(name, offset, shape)] of the parameter blob, in blob order."""
+        n = ctypes.c_int32()
+        self._lib.pn_param_layout(self._ctx, None, 0, ctypes.byref(n))
+        arr = (pn_param_entry * n.value)()
+        _check(self._lib.pn_param_layout(self._ctx, arr, n.value, ctypes.byref(n)), "pn_param_layout")
+        return [(e.name.decode(), int(e.offset), tuple(int(e.shape[k]) for k in range(e.ndim))) for e in arr]
 
     def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64, full=False):
         """Workspace bytes; full=True also covers the full adjoint."""

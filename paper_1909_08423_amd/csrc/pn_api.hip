@@ -2,6 +2,7 @@
 // determinant tables, nuclear-cusp polynomials), workspace planning and the
 // launch sequence of the walker-evaluation path.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -560,6 +561,66 @@ void pn_ctx_destroy(pn_ctx* c) {
 }
 
 int64_t pn_param_count(const pn_ctx* c) { return c ? c->pl.total : -1; }
+
+pn_status pn_param_layout(const pn_ctx* c, pn_param_entry* e, int32_t cap, int32_t* n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !e)) return PN_ERR_INVALID_ARG;
+  const Dims& d = c->d;
+  const ParamLayout& pl = c->pl;
+  int32_t k = 0;
+  auto put = [&](const char* name, int64_t off, int32_t r0, int32_t r1) {
+    if (k < cap) {
+      pn_param_entry& x = e[k];
+      memset(&x, 0, sizeof(x));
+      snprintf(x.name, sizeof(x.name), "%s", name);
+      x.offset = off;
+      x.ndim = r1 > 0 ? 2 : 1;
+      x.shape[0] = r0;
+      x.shape[1] = r1;
+    }
+    ++k;
+  };
+  static const char* chn[3] = {"same", "opp", "nuc"};
+  char buf[32];
+  put("x0", pl.x0, d.DX, 0);
+  put("Y", pl.Y, d.NN, d.DZ);
+  for (int l = 0; l < d.L; ++l) {
+    const ParamLayout::Layer& Lp = pl.layer[l];
+    for (int ch = 0; ch < 3; ++ch) {
+      snprintf(buf, sizeof(buf), "l%d.w_%s.W1", l, chn[ch]);
+      put(buf, Lp.w1W[ch], d.K, d.DZ);
+      snprintf(buf, sizeof(buf), "l%d.w_%s.b1", l, chn[ch]);
+      put(buf, Lp.w1b[ch], d.DZ, 0);
+      snprintf(buf, sizeof(buf), "l%d.w_%s.W2", l, chn[ch]);
+      put(buf, Lp.w2W[ch], d.DZ, d.DZ);
+      snprintf(buf, sizeof(buf), "l%d.w_%s.b2", l, chn[ch]);
+      put(buf, Lp.w2b[ch], d.DZ, 0);
+    }
+    snprintf(buf, sizeof(buf), "l%d.h.W", l);
+    put(buf, Lp.hW, d.DX, d.DZ);
+    snprintf(buf, sizeof(buf), "l%d.h.b", l);
+    put(buf, Lp.hb, d.DZ, 0);
+    for (int ch = 0; ch < 3; ++ch) {
+      snprintf(buf, sizeof(buf), "l%d.g_%s.W", l, chn[ch]);
+      put(buf, Lp.gW[ch], d.DZ, d.DX);
+      snprintf(buf, sizeof(buf), "l%d.g_%s.b", l, chn[ch]);
+      put(buf, Lp.gb[ch], d.DX, 0);
+    }
+  }
+  put("eta.W1", pl.eW1, d.DX, d.DX);
+  put("eta.b1", pl.eb1, d.DX, 0);
+  put("eta.W2", pl.eW2, d.DX, d.DX);
+  put("eta.b2", pl.eb2, d.DX, 0);
+  put("eta.W3", pl.eW3, d.DX, 1);
+  put("eta.b3", pl.eb3, 1, 0);
+  put("kappa.W1", pl.kW1, d.DX, d.DX);
+  put("kappa.b1", pl.kb1, d.DX, 0);
+  put("kappa.W2", pl.kW2, d.DX, d.DX);
+  put("kappa.b2", pl.kb2, d.DX, 0);
+  put("kappa.W3", pl.kW3, d.DX, d.M);
+  put("kappa.b3", pl.kb3, d.M, 0);
+  *n = k;
+  return k <= cap ? PN_OK : PN_ERR_INVALID_ARG;
+}
 
 pn_status pn_workspace_bytes(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
   if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;

@@ -202,3 +202,27 @@ def test_backward_against_finite_differences(pn):
         fm = float((ct * ctx.eval(r, th - e, pn.PN_PREC_FP64, want_derivs=False)["logabs"]).sum())
         fd = (fp - fm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)), (int(k), fd, g[k])
+
+
+def test_param_layout_matches_blob_order(pn):
+    """pn_param_layout names every tensor of the blob at the offsets and
+    shapes the oracle's unpacking of the same blob uses."""
+    from oracle.network import Params
+    w = make_config(2, n_walkers=4)
+    ctx = pn.PauliNetContext(w.system, w.net)
+    lay = ctx.param_layout()
+    n = ctx.param_count
+    p = Params(torch.arange(n, dtype=torch.float64), w.system.nuc_xyz.shape[0], w.system.n_mo, w.net)
+    ref = [("x0", p.x0), ("Y", p.Y)]
+    for l, L in enumerate(p.layers):
+        for c, cn in zip("+-n", ("same", "opp", "nuc")):
+            ref += [(f"l{l}.w_{cn}.{k}", t) for k, t in zip(("W1", "b1", "W2", "b2"), L["w"][c])]
+        ref += [(f"l{l}.h.W", L["h"][0]), (f"l{l}.h.b", L["h"][1])]
+        for c, cn in zip("+-n", ("same", "opp", "nuc")):
+            ref += [(f"l{l}.g_{cn}.W", L["g"][c][0]), (f"l{l}.g_{cn}.b", L["g"][c][1])]
+    ref += [(f"eta.{k}", t) for k, t in zip(("W1", "b1", "W2", "b2", "W3", "b3"), p.eta)]
+    ref += [(f"kappa.{k}", t) for k, t in zip(("W1", "b1", "W2", "b2", "W3", "b3"), p.kappa)]
+    assert [e[0] for e in lay] == [r[0] for r in ref]
+    for (name, off, shape), (_, t) in zip(lay, ref):
+        assert off == int(t.reshape(-1)[0]), name
+        assert shape == tuple(t.shape), name
