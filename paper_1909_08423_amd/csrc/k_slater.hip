@@ -6,7 +6,9 @@
 //
 //  k_slater_value    one wavefront per (walker, determinant, spin): LU with
 //                    partial pivoting (ties to the lowest row), ln|det|,
-//                    sign, and G = A^{-1}.
+//                    sign, and G = A^{-1}; for spin blocks of at most 8
+//                    electrons k_slater_value_lane takes one matrix per lane
+//                    (Gauss-Jordan in registers, same pivoting rule).
 //  k_combine_value   signed log-sum-exp of c_p det_up det_down; weights
 //                    w_p = c_p D_p / Psi_d; ln|psi| = gamma + J + ln|Psi_d|.
 //  k_slater_tangent  one block per (walker, coordinate chunk).  For every
@@ -154,6 +156,126 @@ __global__ __launch_bounds__(kThreads) void k_slater_value(Dims d, DevTables t, 
   }
   wave_sync();
   for (int q = lane; q < n * n; q += 64) G[q] = X[(q / n) * LD + q % n];
+}
+
+// Small determinants (n <= NMAX): one lane per (walker, determinant, spin).
+// Gauss-Jordan inversion in registers with partial pivoting (largest
+// |a[r][c]|, ties to the lowest row): ln|det| and sign from the pivots, then
+// the column swaps undone in reverse order give G = A^{-1}.  Every loop is
+// unrolled over NMAX, so the matrix stays in registers.
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void k_slater_value_lane(Dims d, DevTables t, int64_t nw,
+                                                                const double* __restrict__ phi,
+                                                                const double* __restrict__ fval,
+                                                                double* __restrict__ ginv, double* __restrict__ ldet) {
+  const int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mat >= nw * d.P * 2) return;
+  const int spin = (int)(mat % 2);
+  const int p = (int)((mat / 2) % d.P);
+  const int64_t w = mat / (2 * d.P);
+  const int n = spin == 0 ? d.n_up : d.n_dn;
+  const int e0 = spin == 0 ? 0 : d.n_up;
+  const int* occ = spin == 0 ? t.det_up + p * d.n_up : t.det_dn + p * d.n_dn;
+  const int N = d.N, M = d.M;
+  const int gsz = d.n_up * d.n_up + d.n_dn * d.n_dn;
+  double* G = ginv + (w * d.P + p) * gsz + (spin == 0 ? 0 : d.n_up * d.n_up);
+  double* ld = ldet + ((w * d.P + p) * 2 + spin) * 2;
+  if (n == 0) {
+    ld[0] = 0.0;
+    ld[1] = 1.0;
+    return;
+  }
+  const double* ph = phi + w * N * M * 7;
+  const double* fv = fval + w * N * M;
+  double a[NMAX][NMAX];
+  int oc[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) oc[k] = k < n ? occ[k] : 0;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k)
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      const size_t q = (size_t)(e0 + i) * M + oc[k];
+      a[k][i] = (k < n && i < n) ? ph[q * 7] * fv[q] : (k == i ? 1.0 : 0.0);  // identity padding
+    }
+  int piv[NMAX];
+  double logabs = 0.0, sgn = 1.0;
+  bool singular = false;
+#pragma unroll
+  for (int c = 0; c < NMAX; ++c) {
+    int bi = c;
+    double best = fabs(a[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < NMAX; ++r) {
+      const double v = fabs(a[r][c]);
+      if (r < n && v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    piv[c] = bi;
+    if (bi != c) sgn = -sgn;
+#pragma unroll
+    for (int r = c + 1; r < NMAX; ++r) {
+      if (r == bi) {
+#pragma unroll
+        for (int col = 0; col < NMAX; ++col) {
+          const double tmp = a[c][col];
+          a[c][col] = a[r][col];
+          a[r][col] = tmp;
+        }
+      }
+    }
+    double pv = a[c][c];
+    if (c < n) {
+      if (pv == 0.0) {
+        singular = true;
+        pv = 1.0;
+      }
+      logabs += log(fabs(pv));
+      if (pv < 0) sgn = -sgn;
+    }
+    const double inv = 1.0 / pv;
+    a[c][c] = 1.0;
+#pragma unroll
+    for (int col = 0; col < NMAX; ++col) a[c][col] *= inv;
+#pragma unroll
+    for (int r = 0; r < NMAX; ++r) {
+      if (r == c) continue;
+      const double f = a[r][c];
+      a[r][c] = 0.0;
+#pragma unroll
+      for (int col = 0; col < NMAX; ++col) a[r][col] -= f * a[c][col];
+    }
+  }
+  // undo the row interchanges as column interchanges, last first
+#pragma unroll
+  for (int c = NMAX - 1; c >= 0; --c) {
+#pragma unroll
+    for (int col = c + 1; col < NMAX; ++col) {
+      if (piv[c] == col) {
+#pragma unroll
+        for (int r = 0; r < NMAX; ++r) {
+          const double tmp = a[r][c];
+          a[r][c] = a[r][col];
+          a[r][col] = tmp;
+        }
+      }
+    }
+  }
+  if (singular) {
+    ld[0] = -INFINITY;
+    ld[1] = 0.0;
+  } else {
+    ld[0] = logabs;
+    ld[1] = sgn;
+  }
+  // a now holds A^{-1}[electron][orbital slot]
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+      if (i < n && k < n) G[i * n + k] = singular ? 0.0 : a[i][k];
 }
 
 __global__ __launch_bounds__(kThreads) void k_combine_value(Dims d, DevTables t, int64_t nw,
@@ -375,12 +497,19 @@ void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, c
                          double* sign) {
   const Dims& d = c->d;
   const int NM = std::max(d.n_up, d.n_dn);
-  size_t lds = (size_t)kWaves * 2 * NM * (NM + 1) * sizeof(double) + kWaves * kMaxSpin * sizeof(int);
   int64_t nmat = nw * d.P * 2;
-  int64_t nb = (nmat + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_slater_value, dim3((unsigned)nb), dim3(kThreads), lds, s, d, c->t, nw,
-                     reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
-                     reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet));
+  if (NM <= 8) {
+    auto kern = NM <= 4 ? &k_slater_value_lane<4> : (NM <= 6 ? &k_slater_value_lane<6> : &k_slater_value_lane<8>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nmat + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d, c->t, nw,
+                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
+                       reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet));
+  } else {
+    size_t lds = (size_t)kWaves * 2 * NM * (NM + 1) * sizeof(double) + kWaves * kMaxSpin * sizeof(int);
+    int64_t nb = (nmat + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(k_slater_value, dim3((unsigned)nb), dim3(kThreads), lds, s, d, c->t, nw,
+                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
+                       reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet));
+  }
   int64_t nb2 = (nw + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_combine_value, dim3((unsigned)nb2), dim3(kThreads), 0, s, d, c->t, nw,
                      reinterpret_cast<const double*>(ws + L.geo), reinterpret_cast<const double*>(ws + L.jval),

@@ -41,8 +41,27 @@ constexpr int kThreadsT = 256;
 
 namespace {
 
+// Block-wide copy of n 16-byte units: every thread issues the four loads of
+// a round before its stores, so a copy costs about one memory latency per
+// round of 4 * blockDim units rather than one per element.
+__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int n) {
+  const int nt = (int)blockDim.x, t0 = (int)threadIdx.x;
+  const uint4 z = {0u, 0u, 0u, 0u};
+  for (int base = 0; base < n; base += 4 * nt) {
+    const int q0 = base + t0, q1 = q0 + nt, q2 = q1 + nt, q3 = q2 + nt;
+    const uint4 v0 = q0 < n ? src[q0] : z;
+    const uint4 v1 = q1 < n ? src[q1] : z;
+    const uint4 v2 = q2 < n ? src[q2] : z;
+    const uint4 v3 = q3 < n ? src[q3] : z;
+    if (q0 < n) dst[q0] = v0;
+    if (q1 < n) dst[q1] = v1;
+    if (q2 < n) dst[q2] = v2;
+    if (q3 < n) dst[q3] = v3;
+  }
+}
+
 template <typename TN, int C, bool STAGE>
-__global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
+__global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
                                                            const double* __restrict__ r, const TN* __restrict__ P,
                                                            ParamLayout pl, const TN* __restrict__ filt,
                                                            const TN* __restrict__ hval, const TN* __restrict__ kcoef,
@@ -87,7 +106,12 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
-  for (int q = threadIdx.x; q < R * LDX; q += blockDim.x) XT[q] = 0;
+  {
+    const uint4 z4 = {0u, 0u, 0u, 0u};
+    uint4* x4 = reinterpret_cast<uint4*>(XT);
+    for (int q = threadIdx.x; q < R * LDX * (int)sizeof(TN) / 16; q += blockDim.x) x4[q] = z4;
+  }
+  constexpr int V = 16 / sizeof(TN);  // elements per 16-byte unit
   __syncthreads();
   for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
     const int k = e_lo + q / N, i = q % N;
@@ -114,19 +138,41 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
     const TN* fd = fw + (int64_t)d.n_pairs * DZ;       // w'/d
     const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
     const TN* hv = hval + (w * d.L + n) * N * DZ;
-    for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) hvs[q] = hv[q];
+    copy16(reinterpret_cast<uint4*>(hvs), reinterpret_cast<const uint4*>(hv), N * DZ / V);
     // the adjoint pass re-reads the layer inputs x^(n), n >= 1 (x^(0) has no tangents)
     if (xsave && n > 0) {
       TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (n - 1)) * R * DX;
       for (int q = threadIdx.x; q < R * DX; q += blockDim.x) xs[q] = XT[(q / DX) * LDX + q % DX];
     }
     if constexpr (STAGE) {
-      for (int q = threadIdx.x; q < d.n_ee * DZ; q += blockDim.x) wvs[q] = fv[q];
-      for (int q = threadIdx.x; q < NCE * NP * DZ; q += blockDim.x) {
-        const int k = e_lo + q / (NP * DZ), part = (q / DZ) % NP, z = q % DZ;
-        const int64_t p = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
-        wds[q] = p >= 0 ? fd[p * DZ + z] : TN(0);
-        w2s[q] = p >= 0 ? f2[p * DZ + z] : TN(0);
+      copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(fv), d.n_ee * DZ / V);
+      // rows (chunk electron k, partner) of w'/d and w'': 16-byte units, two
+      // rounds of loads in flight per thread
+      const int U16 = DZ / V, n16 = NCE * NP * U16;
+      const uint4 z4 = {0u, 0u, 0u, 0u};
+      for (int base = 0; base < n16; base += 2 * (int)blockDim.x) {
+        const int q0 = base + (int)threadIdx.x, q1 = q0 + (int)blockDim.x;
+        int64_t p0 = -1, p1 = -1;
+        if (q0 < n16) {
+          const int row = q0 / U16, k = e_lo + row / NP, part = row % NP;
+          p0 = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
+        }
+        if (q1 < n16) {
+          const int row = q1 / U16, k = e_lo + row / NP, part = row % NP;
+          p1 = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
+        }
+        const uint4 a0 = p0 >= 0 ? reinterpret_cast<const uint4*>(fd + p0 * DZ)[q0 % U16] : z4;
+        const uint4 b0 = p0 >= 0 ? reinterpret_cast<const uint4*>(f2 + p0 * DZ)[q0 % U16] : z4;
+        const uint4 a1 = p1 >= 0 ? reinterpret_cast<const uint4*>(fd + p1 * DZ)[q1 % U16] : z4;
+        const uint4 b1 = p1 >= 0 ? reinterpret_cast<const uint4*>(f2 + p1 * DZ)[q1 % U16] : z4;
+        if (q0 < n16) {
+          reinterpret_cast<uint4*>(wds)[q0] = a0;
+          reinterpret_cast<uint4*>(w2s)[q0] = b0;
+        }
+        if (q1 < n16) {
+          reinterpret_cast<uint4*>(wds)[q1] = a1;
+          reinterpret_cast<uint4*>(w2s)[q1] = b1;
+        }
       }
     }
     if (n > 0) gemm_mfma<TN>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
@@ -270,6 +316,15 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
     TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (d.L - 1)) * R * DX;
     for (int q = threadIdx.x; q < R * DX; q += blockDim.x) xs[q] = XT[(q / DX) * LDX + q % DX];
   }
+  // The heads' activation slopes (kappa [2][2][N][DX], then eta [2][2][DX])
+  // go to the staging region, which the layers no longer need; the copy is
+  // issued before the Jastrow sum so its latency overlaps that work.
+  const int nce_max = min(N, T / 3 + 2);
+  const bool hstage = STAGE && d.n_ee * DZ + 2 * nce_max * NP * DZ >= 4 * N * DX + 4 * DX;
+  if (hstage) {
+    copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V);
+    copy16(reinterpret_cast<uint4*>(wvs + 4 * N * DX), reinterpret_cast<const uint4*>(ecoef + w * 4 * DX), 4 * DX / V);
+  }
   // ---- Jastrow head on sum_i x_i, rows = columns ----
   TN* S0 = ES;             // [C][LDX]
   TN* S1 = ES + C * LDX;   // [C][LDX]
@@ -285,7 +340,7 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
     TN* Sout = lay == 0 ? S1 : S0;
     gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
     __syncthreads();
-    const TN* ec = ecoef + (w * 2 + lay) * 2 * DX;
+    const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
     for (int x = threadIdx.x; x < DX; x += blockDim.x) {
       const TN s1 = ec[x], s2 = ec[DX + x];
       TN sq = 0;
@@ -315,7 +370,7 @@ __global__ __launch_bounds__(kThreadsT) void k_net_tangent(Dims d, DevTables t, 
   __syncthreads();
   for (int lay = 0; lay < 2; ++lay) {
     TN* A = lay == 0 ? KT : XT;
-    const TN* kc = kcoef + (w * 2 + lay) * 2 * N * DX;
+    const TN* kc = hstage ? wvs + lay * 2 * N * DX : kcoef + (w * 2 + lay) * 2 * N * DX;
     for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
       const int i = q / DX, x = q % DX;
       const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
