@@ -133,8 +133,23 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
       const int r = min((rt << 4) + c16, rows - 1);
       const TN* xr = X + (size_t)r * ldx + g * KQ;
       TN afrag[KQ];
+      // 16-byte reads: each group of 8 lanes then covers every LDS bank once
+      // (rows are padded by 16 bytes); element-wise reads of the same rows
+      // hit each bank up to four times.  Rows and lane-group offsets are
+      // 16-byte aligned for every caller (row strides from ld_pad, KQ * size
+      // a multiple of 16 bytes).
+      if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
+        constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
+        const uint4* xv = reinterpret_cast<const uint4*>(xr);
 #pragma unroll
-      for (int s = 0; s < KQ; ++s) afrag[s] = xr[s];
+        for (int k = 0; k < NV; ++k) {
+          const uint4 q = xv[k];
+          __builtin_memcpy(&afrag[k * PV], &q, 16);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KQ; ++s) afrag[s] = xr[s];
+      }
       acc_t c;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
