@@ -60,14 +60,18 @@ __device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __r
   }
 }
 
-template <typename TN, int C, bool STAGE>
+// BF16 is a template parameter so that the FP32 and FP64 instantiations
+// carry no BF16 operand code (smaller kernels, fewer instruction-cache
+// misses).
+template <typename TN, int C, bool STAGE, bool BF16>
 __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
                                                            const double* __restrict__ r, const TN* __restrict__ P,
                                                            ParamLayout pl, const TN* __restrict__ filt,
                                                            const TN* __restrict__ hval, const TN* __restrict__ kcoef,
                                                            const TN* __restrict__ ecoef, double* __restrict__ ftan,
                                                            double* __restrict__ jtan, TN* __restrict__ xsave,
-                                                           bool bf16) {
+                                                           bool) {
+  constexpr bool bf16 = BF16;
   constexpr int T = C - 1, LC = T;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
@@ -403,14 +407,22 @@ template <typename TN, int C, bool STAGE>
 void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
               bool bf16, TN* xsave) {
   const int64_t nb = nw * L.n_chunks;
-  if (L.lds_tangent > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_net_tangent<TN, C, STAGE>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_tangent);
-  hipLaunchKernelGGL((k_net_tangent<TN, C, STAGE>), dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d,
-                     c->t, nw, L.n_chunks, r, P, c->pl, reinterpret_cast<const TN*>(ws + L.filt),
-                     reinterpret_cast<const TN*>(ws + L.hval), reinterpret_cast<const TN*>(ws + L.kcoef),
-                     reinterpret_cast<const TN*>(ws + L.ecoef), reinterpret_cast<double*>(ws + L.ftan),
-                     reinterpret_cast<double*>(ws + L.jtan), xsave, bf16);
+  auto go = [&](auto kern) {
+    if (L.lds_tangent > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)L.lds_tangent);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d, c->t, nw, L.n_chunks, r, P,
+                       c->pl, reinterpret_cast<const TN*>(ws + L.filt), reinterpret_cast<const TN*>(ws + L.hval),
+                       reinterpret_cast<const TN*>(ws + L.kcoef), reinterpret_cast<const TN*>(ws + L.ecoef),
+                       reinterpret_cast<double*>(ws + L.ftan), reinterpret_cast<double*>(ws + L.jtan), xsave, bf16);
+  };
+  if constexpr (sizeof(TN) == sizeof(float)) {
+    if (bf16) {
+      go(&k_net_tangent<TN, C, STAGE, true>);
+      return;
+    }
+  }
+  go(&k_net_tangent<TN, C, STAGE, false>);
 }
 
 template <typename TN, bool STAGE>
