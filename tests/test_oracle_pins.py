@@ -676,3 +676,59 @@ def test_full_adjoint_reduces_to_value_adjoint():
     a = o.param_grad_full(w.walkers, ct_logabs=ct)
     b = o.param_grad_logabs(w.walkers, ct)
     assert torch.allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Langevin --
+def _toy_randoms(B, n, seed):
+    g = torch.Generator().manual_seed(seed)
+    return lambda k: (torch.randn(B, n, generator=g, dtype=torch.float64),
+                      torch.rand(B, generator=g, dtype=torch.float64))
+
+
+def test_langevin_samples_gaussian_exactly():
+    """|psi|^2 = exp(-2 a r^2) (a = 1/2): per-coordinate variance 1/(4a).
+    At tau = 0.4 the drift-diffusion chain without the Hastings correction
+    would sit at 1/(2 - tau) = 0.625; the sampler must give 0.5."""
+    from oracle.langevin import langevin_run
+    a = 0.5
+
+    def lg(r):
+        r = torch.as_tensor(r, dtype=torch.float64)
+        return -a * (r ** 2).sum((1, 2)), -2 * a * r
+
+    B = 4000
+    r0 = torch.randn(B, 1, 3, generator=torch.Generator().manual_seed(1), dtype=torch.float64)
+    r, accs, _, _ = langevin_run(lg, r0, torch.zeros(0, 3, dtype=torch.float64), 0.4, _toy_randoms(B, 3, 2), 80,
+                                 rate=0.0)
+    var = float((r ** 2).mean())
+    assert abs(var - 1 / (4 * a)) < 0.025, var
+    assert 0.5 < sum(accs[-20:]) / 20 < 1.0
+
+
+def test_langevin_hydrogen_mean_radius_with_clipping():
+    """Hydrogen ground state psi = exp(-r): <r> = 3/2 bohr under |psi|^2, with
+    the nearest-nucleus clipping of the drift active (the drift length tau
+    would exceed r near the nucleus)."""
+    from oracle.langevin import langevin_run
+
+    def lg(r):
+        r = torch.as_tensor(r, dtype=torch.float64)
+        d = torch.linalg.norm(r, dim=-1)
+        return -d.sum(-1), -r / d[..., None]
+
+    B = 4000
+    r0 = torch.randn(B, 1, 3, generator=torch.Generator().manual_seed(3), dtype=torch.float64)
+    r, accs, taus, _ = langevin_run(lg, r0, torch.zeros(1, 3, dtype=torch.float64), 0.5, _toy_randoms(B, 3, 4), 120)
+    mean_r = float(torch.linalg.norm(r, dim=-1).mean())
+    assert abs(mean_r - 1.5) < 0.05, mean_r
+    assert abs(sum(accs[-40:]) / 40 - 0.57) < 0.08  # the step adapts to the target acceptance
+
+
+def test_langevin_drift_clipped_below_nearest_nucleus():
+    from oracle.langevin import clipped_drift
+    nuc = torch.tensor([[0.0, 0.0, 0.0], [0.0, 0.0, 3.0]], dtype=torch.float64)
+    r = torch.tensor([[[0.1, 0.0, 0.0], [0.0, 0.0, 2.2]]], dtype=torch.float64)
+    g = torch.tensor([[[-50.0, 0.0, 0.0], [0.0, 0.2, 0.0]]], dtype=torch.float64)
+    d = clipped_drift(r, g, nuc, 0.1)
+    assert torch.allclose(torch.linalg.norm(d[0, 0]), torch.tensor(0.1, dtype=torch.float64))  # clipped to 0.1
+    assert torch.allclose(d[0, 1], 0.1 * g[0, 1])  # short drift untouched
