@@ -186,6 +186,37 @@ pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walk
                            const double* ct_logabs, const double* ct_grad, const double* ct_lap,
                            const double* ct_eloc, double* grad_params, void* ws, size_t ws_bytes);
 
+/* ---- Langevin Monte Carlo sampling ----------------------------------------
+ * Methods, "Ansatz optimization" (Table 2: target acceptance 57 %, 50
+ * discarded steps, 1 decorrelation step, resampling every 100 iterations):
+ * drift-diffusion moves of Umrigar et al. (1993) with the step clipped below
+ * the nearest-nucleus distance.  Per walker and step, all electrons at once:
+ *   d_i = tau d_i ln|psi|, rescaled to length <= min_I |r_i - R_I|;
+ *   r' = r + d(r) + sqrt(tau) xi;
+ *   accept if u < A, ln A = 2 (ln|psi(r')| - ln|psi(r)|)
+ *                         - (|r - r' - d(r')|^2 - |r' - r - d(r)|^2) / (2 tau);
+ *   after the step tau <- tau exp(adapt_rate (acceptance - target_accept)).
+ * xi and u come from Philox4x32-10 keyed by `seed`, counter (walker, step,
+ * call, 0) as in pn_vmc_step (step = step0 + k for the k-th step). */
+typedef struct {
+  double target_accept; /* in (0, 1); 0.57 in the paper */
+  double adapt_rate;    /* >= 0; 0 keeps tau fixed */
+} pn_langevin_hparams;
+
+pn_status pn_langevin_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+
+/* n_steps steps on the walkers r ([B][n_elec][3] FP64, updated in place).
+ * tau: [1] FP64 device scalar, read at every step and updated by the
+ * adaptation (so consecutive calls continue the schedule).  stats:
+ * [n_steps][2] FP64 device output (acceptance of the step, tau used).  One
+ * wavefunction evaluation (value and gradient) per step plus one at the
+ * start; the discarded and decorrelation steps of a schedule are simply
+ * more steps. */
+pn_status pn_langevin_run(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers, double* r,
+                          const double* params, pn_precision prec, const pn_langevin_hparams* hp,
+                          double* tau, int32_t n_steps, uint64_t seed, int64_t step0, double* stats,
+                          void* ws, size_t ws_bytes);
+
 /* ---- one VMC step of a job (serving) -------------------------------------
  * Methods, "Ansatz optimization": the walkers sample |psi|^2 by Metropolis
  * moves, the loss is the mean clipped local energy, its gradient comes from

@@ -13,6 +13,7 @@ from ._lib import (  # noqa: F401
     PauliNetContext,
     PauliNetError,
     library_path,
+    langevin_run,
     load_library,
     paulinet_eval,
     vmc_step,

@@ -60,6 +60,10 @@ class pn_param_entry(ctypes.Structure):
                 ("shape", ctypes.c_int32 * 2)]
 
 
+class pn_langevin_hparams(ctypes.Structure):
+    _fields_ = [("target_accept", ctypes.c_double), ("adapt_rate", ctypes.c_double)]
+
+
 class pn_vmc_hparams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("sigma", "lr0", "t0", "clip_q", "beta1", "beta2", "eps", "weight_decay")]
@@ -125,6 +129,11 @@ def load_library():
     lib.pn_stage_timing.restype = i32
     lib.pn_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.pn_stage_times.restype = i32
+    lib.pn_langevin_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_langevin_workspace_bytes.restype = i32
+    lib.pn_langevin_run.argtypes = [vp, vp, i64, vp, vp, i32, ctypes.POINTER(pn_langevin_hparams), vp, i32,
+                                    ctypes.c_uint64, i64, vp, vp, ctypes.c_size_t]
+    lib.pn_langevin_run.restype = i32
     lib.pn_vmc_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pn_vmc_workspace_bytes.restype = i32
     lib.pn_vmc_step.argtypes = [vp, vp, ctypes.POINTER(pn_vmc_job), i32, ctypes.POINTER(pn_vmc_hparams), vp,
@@ -378,3 +387,27 @@ def vmc_step(ctx, state, prec, hparams=None, stream=None):
     ws = state["ws"]
     _check(ctx._lib.pn_vmc_step(ctx._ctx, ctypes.c_void_p(st.cuda_stream), ctypes.byref(j), int(prec),
                                 ctypes.byref(h), ctypes.c_void_p(ws.data_ptr()), ws.numel()), "pn_vmc_step")
+
+
+def langevin_run(ctx, r, params, prec, tau, n_steps, seed, step0=0, target_accept=0.57, adapt_rate=1.0,
+                 ws=None, stream=None):
+    """n_steps Langevin steps on r ([B, N, 3] float64 device tensor, updated
+    in place); tau: [1] float64 device tensor (updated).  Returns the
+    [n_steps, 2] device tensor of (acceptance, tau used)."""
+    import torch
+    for name, t in (("r", r), ("params", params), ("tau", tau)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise PauliNetError(f"{name} must be a contiguous float64 device tensor")
+    B = int(r.shape[0])
+    if ws is None:
+        b = ctypes.c_size_t()
+        _check(ctx._lib.pn_langevin_workspace_bytes(ctx._ctx, B, int(prec), ctypes.byref(b)),
+               "pn_langevin_workspace_bytes")
+        ws = torch.empty(int(b.value), dtype=torch.uint8, device=r.device)
+    stats = torch.empty(max(int(n_steps), 1), 2, dtype=torch.float64, device=r.device)
+    hp = pn_langevin_hparams(float(target_accept), float(adapt_rate))
+    s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    _check(ctx._lib.pn_langevin_run(ctx._ctx, s, B, _ptr(r), _ptr(params), int(prec), ctypes.byref(hp), _ptr(tau),
+                                    int(n_steps), ctypes.c_uint64(int(seed)), int(step0), _ptr(stats), _ptr(ws),
+                                    ws.numel()), "pn_langevin_run")
+    return stats[:n_steps]

@@ -12,32 +12,11 @@
 // acceptance uniform.
 #include <math.h>
 
+#include "philox.h"
 #include "pn_internal.h"
 
 namespace pn {
 namespace {
-
-constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u, kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
-constexpr uint32_t kAcceptCall = 0xFFFFFFFFu;
-
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int rnd = 0; rnd < 10; ++rnd) {
-    const uint32_t hi0 = __umulhi(kM0, c[0]), lo0 = kM0 * c[0];
-    const uint32_t hi1 = __umulhi(kM1, c[2]), lo1 = kM1 * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += kW0;
-    k1 += kW1;
-  }
-}
-
-__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
-  return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
-}
 
 __global__ __launch_bounds__(kThreads) void k_propose(int64_t nw, int ncoord, const double* __restrict__ r,
                                                       double* __restrict__ rp, double sigma, uint64_t seed,
