@@ -68,14 +68,22 @@ def chunk_T(s, net, prec):
             e += n_ee * DZ + 2 * NCE * (N + NN) * DZ
         return 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + e * tn
 
-    for stage in (True, False):
-        for nc in range(1, 3 * N + 1):
-            T = -(-3 * N // nc)
-            if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
-                continue
-            if lds(T, stage) <= 80 * 1024 or (not stage and T == 1):
-                return T
-    return 1
+    def pick(budget):
+        for stage in (True, False):
+            for nc in range(1, 3 * N + 1):
+                T = -(-3 * N // nc)
+                if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
+                    continue
+                if lds(T, stage) <= budget or (not stage and T == 1):
+                    return T
+        return 1
+
+    T = pick(80 * 1024)
+    if T < 3:
+        T2 = pick(160 * 1024)
+        if T2 >= 2 * T:
+            T = T2
+    return T
 
 
 TANGENT_SOURCES = ["k_tangent_impl.h", "k_tangent_f32.hip", "k_tangent_f64.hip", "mfma_gemm.h", "gemm_lds.h"]
@@ -142,6 +150,39 @@ def time_path(ctx, r, th, prec, steps, warmup, torch):
     return dt, out, stages
 
 
+def other_workloads(pn, torch, steps=3, warmup=1):
+    """The other synthetic systems at their full batch sizes: H2 (launch
+    bound: microseconds per batch), H10 in BF16 / FP32 / FP64 and the
+    30-electron diatomic in FP32 / FP64; walker E_loc evaluations per
+    second and the mean E_loc difference to the FP64 path."""
+    from synth import make_config
+    P = pn._lib.PRECISIONS
+    plan = {1: ["fp64"], 3: ["bf16", "fp32", "fp64"], 5: ["fp32", "fp64"]}
+    out = {}
+    for idx, precs in plan.items():
+        w = make_config(idx)
+        ctx = pn.PauliNetContext(w.system, w.net)
+        r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+        th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+        B = w.walkers.shape[0]
+        rec = {"walkers": B}
+        e64 = None
+        for prec in reversed(precs):  # FP64 first, as the reference of the others
+            dt, o, _ = time_path(ctx, r, th, P[prec], steps, warmup, torch)
+            e = o["eloc"].double().cpu().numpy().copy()
+            if prec == "fp64":
+                e64 = e
+            ent = {"walker_evals_per_s": B * steps / dt, "us_per_batch": dt / steps * 1e6}
+            if prec != "fp64" and e64 is not None:
+                de = np.abs(e - e64)
+                ent["abs_dmean_eloc_Ha"] = float(abs(e.mean() - e64.mean()))
+                ent["p99_abs_deloc_Ha"] = float(np.percentile(de, 99))
+            rec[prec] = ent
+        ctx.close()
+        out[w.name] = rec
+    return out
+
+
 def cpu_baseline(workload_idx, budget_s=15.0, chunk=8):
     import torch
     from oracle import Oracle
@@ -206,6 +247,23 @@ def time_full_adjoint(ctx, r, th, prec, steps, warmup, torch):
             "workspace_GiB": ws.numel() / 2**30}
 
 
+def time_langevin(pn, ctx, w, prec, steps, torch):
+    """Langevin sampling (drift-diffusion + Metropolis-Hastings, adaptive
+    step) on the benchmark batch: walker-steps per second."""
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    tau = torch.tensor([0.05], dtype=torch.float64, device="cuda")
+    pn.langevin_run(ctx, r, th, prec, tau, 2, seed=11, step0=0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = pn.langevin_run(ctx, r, th, prec, tau, steps, seed=11, step0=2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = st.cpu().numpy()
+    return {"walker_steps_per_s": r.shape[0] * steps / dt, "ms_per_step": dt / steps * 1e3, "steps": steps,
+            "last_acceptance": float(st[-1, 0]), "last_tau": float(st[-1, 1])}
+
+
 def run_serving(pn, prec, n_jobs, n_steps, torch, mean_gap_s=0.05, budget_gib=64):
     """The serving stream (H-chains and atoms, 2-18 electrons, 1-32
     determinants, 1024-8192 walkers, Poisson arrivals): n_jobs jobs of
@@ -244,6 +302,7 @@ def main():
     ap.add_argument("--serve-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-full-adjoint", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the other workloads")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -330,6 +389,9 @@ def main():
     if probe is not None:
         res["copy_probe"] = probe
     res["vmc_step"] = time_vmc_step(pn, ctx, w, P[args.prec], max(3, args.steps // 4), 1, torch)
+    if not args.no_other:
+        res["other_workloads"] = other_workloads(pn, torch)
+    res["langevin"] = time_langevin(pn, ctx, w, P[args.prec], max(5, args.steps // 2), torch)
     if not args.no_full_adjoint:
         res["full_adjoint_eloc"] = {
             args.prec: time_full_adjoint(ctx, r, th, P[args.prec], max(3, args.steps // 4), 1, torch),

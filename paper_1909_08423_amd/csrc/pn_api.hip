@@ -164,23 +164,39 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
   L.full = full;
   // chunking of the 3N coordinates for the tangent pass: the largest chunk
   // whose block fits the LDS budget, preferring the form that stages the
-  // filter tables in LDS
-  const size_t budget = 80 * 1024;  // two 256-thread blocks per CU
+  // filter tables in LDS.  Two 256-thread blocks per CU (80 KB each) unless
+  // that leaves chunks of fewer than 3 coordinates (large systems, where the
+  // per-chunk work of the heads would be repeated 3N times): then one block
+  // per CU with all 160 KB, if that at least doubles the chunk.
   const int ncoord = 3 * d.N;
   auto lds_of = [&](int T, bool stage) {
     return fp64 ? tangent_lds_bytes<double>(d, T, stage) : tangent_lds_bytes<float>(d, T, stage);
   };
-  L.T = 0;
-  for (int pass = 0; pass < 2 && L.T == 0; ++pass) {
-    const bool stage = pass == 0;
-    for (int nc = 1; nc <= ncoord; ++nc) {
-      const int T = (ncoord + nc - 1) / nc;
-      if (!tangent_chunk_supported(T)) continue;
-      if (lds_of(T, stage) <= budget || (!stage && T == 1)) {
-        L.T = T;
-        L.stage_filters = stage;
-        break;
+  auto pick = [&](size_t budget, int& T_out, bool& stage_out) {
+    T_out = 0;
+    for (int pass = 0; pass < 2 && T_out == 0; ++pass) {
+      const bool stage = pass == 0;
+      for (int nc = 1; nc <= ncoord; ++nc) {
+        const int T = (ncoord + nc - 1) / nc;
+        if (!tangent_chunk_supported(T)) continue;
+        if (lds_of(T, stage) <= budget || (!stage && T == 1)) {
+          T_out = T;
+          stage_out = stage;
+          break;
+        }
       }
+    }
+  };
+  size_t budget = 80 * 1024;
+  pick(budget, L.T, L.stage_filters);
+  if (L.T < 3) {
+    int T2;
+    bool st2;
+    pick(kLdsMax, T2, st2);
+    if (T2 >= 2 * L.T) {
+      budget = kLdsMax;
+      L.T = T2;
+      L.stage_filters = st2;
     }
   }
   if (full) {
