@@ -104,7 +104,16 @@ typedef struct {
   int32_t dim_x;      /* D_x, electron embedding width                  */
   int32_t dim_z;      /* D_z, message width                             */
   int32_t n_layers;   /* L, interaction layers                          */
+  int32_t flags;      /* ansatz variant: PN_NET_NO_JASTROW, PN_NET_NO_BACKFLOW (or 0) */
 } pn_net_desc;
+
+/* Ansatz variants (Results: the paper compares single- and multi-determinant
+ * baselines with a Jastrow factor only or with Jastrow and backflow; single
+ * vs multiple determinants is just n_det).  A removed head is identically
+ * J = 0 or f = 1: its parameters stay in the blob but receive exactly zero
+ * gradient, and with both heads removed the network is not evaluated. */
+#define PN_NET_NO_JASTROW 1
+#define PN_NET_NO_BACKFLOW 2
 
 /* Create a context: validates shapes, builds the pair and determinant
  * tables and the nuclear-cusp polynomials on the host, copies them to the

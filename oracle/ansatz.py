@@ -95,7 +95,17 @@ class Oracle:
         else:
             p = self.p
         gamma = electronic_cusp(r, self.n_up)
-        J, f = jastrow_backflow(r, self.R, self.n_up, p, self.net)
+        flags = int(getattr(self.net, "flags", 0))
+        if flags & 3 == 3:  # neither head: the network does not enter
+            J, f = torch.zeros(r.shape[0], dtype=r.dtype), torch.ones(r.shape[0], r.shape[1], self.system.n_mo,
+                                                                        dtype=r.dtype)
+            J = J + 0.0 * p.flat.sum()  # keep the parameters in the graph (zero gradient)
+        else:
+            J, f = jastrow_backflow(r, self.R, self.n_up, p, self.net)
+            if flags & 1:  # variant without Jastrow factor: J = 0
+                J = 0.0 * J
+            if flags & 2:  # variant without backflow: f = 1
+                f = 1.0 + 0.0 * f
         (su, lu), (sd, ld) = self.slater_logdets(r, f)
         lc = torch.log(torch.abs(self.ci))
         l_p = lc + lu + ld

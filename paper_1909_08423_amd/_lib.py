@@ -52,6 +52,7 @@ class pn_net_desc(ctypes.Structure):
         ("dim_x", ctypes.c_int32),
         ("dim_z", ctypes.c_int32),
         ("n_layers", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -189,6 +190,7 @@ class PauliNetContext:
         n = pn_net_desc()
         n.n_feat, n.feat_cutoff = int(net.n_feat), float(net.feat_cutoff)
         n.dim_x, n.dim_z, n.n_layers = int(net.dim_x), int(net.dim_z), int(net.n_layers)
+        n.flags = int(getattr(net, "flags", 0))
         out = ctypes.c_void_p()
         _check(lib.pn_ctx_create(ctypes.byref(s), ctypes.byref(n), ctypes.byref(out)), "pn_ctx_create")
         self._ctx = out

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
     const int R = nwb * N;
     __syncthreads();
     for (int q = threadIdx.x; q < nwb; q += blockDim.x) cw[q] = (TN)ct_logabs[w0 + q];
+    const TN jas = (d.flags & PN_NET_NO_JASTROW) ? TN(0) : TN(1);  // a removed Jastrow factor gets no cotangent
     // ---- cotangent of the backflow, from the determinants ----
     for (int q = threadIdx.x; q < R * LDM; q += blockDim.x) CF[q] = 0;
     for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
@@ -92,7 +93,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         for (int k = 0; k < n; ++k) CF[row * LDM + dets[p * n + k]] += (TN)(wp * G[ii * n + k]);
       }
       const double* ph = phi + (w * N + i) * M * 7;
-      if (ctfpart) {
+      if (d.flags & PN_NET_NO_BACKFLOW) {
+        for (int mu = 0; mu < M; ++mu) CF[row * LDM + mu] = 0;  // f = 1 does not depend on theta
+      } else if (ctfpart) {
         // full adjoint: the determinant part supplies the cotangent of f
         // (its ln|psi| share included), summed over the coordinate chunks
         for (int mu = 0; mu < M; ++mu) {
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
         U2[r * LDX + x] += P[pl.eb2 + x];
         // d/d u2 = cJ * W3[x] * ssp'(u2)
         const TN u2 = U2[r * LDX + x];
-        TN c2 = cw[r] * P[pl.eW3 + x] * sig(u2);
+        TN c2 = jas * cw[r] * P[pl.eW3 + x] * sig(u2);
         if (ctec) {  // tangent-pass cotangents of ssp'(u2), ssp''(u2)
           const TN* ce = ctec + ((w0 + r) * 2 + 1) * 2 * DX;
           c2 += ce[x] * ssp2(u2) + ce[DX + x] * ssp3(u2);
@@ -146,12 +149,12 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
       // dW3, db3
       for (int x = threadIdx.x; x < DX; x += blockDim.x) {
         TN s = 0;
-        for (int r = 0; r < nwb; ++r) s += ssp(U2[r * LDX + x]) * cw[r];
+        for (int r = 0; r < nwb; ++r) s += jas * ssp(U2[r * LDX + x]) * cw[r];
         slot[pl.eW3 + x] = first ? s : slot[pl.eW3 + x] + s;
       }
       if (threadIdx.x == 0) {
         TN s = 0;
-        for (int r = 0; r < nwb; ++r) s += cw[r];
+        for (int r = 0; r < nwb; ++r) s += jas * cw[r];
         slot[pl.eb3] = first ? s : slot[pl.eb3] + s;
       }
       outer_mfma<TN, true>(U1, LDX, DX, C2, LDX, DX, nwb, slot + pl.eW2, first);

@@ -90,32 +90,40 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
   // ---- Jastrow head on s = sum_i x_i (rows = walkers) ----
   TN* S = E;                // [WPB][LDX]
   TN* U = E + WPB * LDX;    // [WPB][LDX]
-  for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
-    int wl = q / DX, x = q % DX;
-    TN s = 0;
-    for (int i = 0; i < N; ++i) s += X[(wl * N + i) * LDX + x];
-    S[wl * LDX + x] = s;
-  }
-  __syncthreads();
-  for (int lay = 0; lay < 2; ++lay) {
-    gemm_mfma<TN>(S, LDX, nwb, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, U, LDX, false, bf16);
-    __syncthreads();
+  if (d.flags & PN_NET_NO_JASTROW) {
+    for (int wl = threadIdx.x; wl < nwb; wl += blockDim.x) jval[w0 + wl] = 0.0;
+  } else {
     for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
       int wl = q / DX, x = q % DX;
-      TN u = U[wl * LDX + x] + P[(lay == 0 ? pl.eb1 : pl.eb2) + x];
-      TN sg = sigmoid_d(u);
-      ecoef[((w0 + wl) * 2 + lay) * 2 * DX + x] = sg;
-      ecoef[((w0 + wl) * 2 + lay) * 2 * DX + DX + x] = sg * (TN(1) - sg);
-      S[wl * LDX + x] = ssp(u);
+      TN s = 0;
+      for (int i = 0; i < N; ++i) s += X[(wl * N + i) * LDX + x];
+      S[wl * LDX + x] = s;
     }
     __syncthreads();
-  }
-  for (int wl = threadIdx.x; wl < nwb; wl += blockDim.x) {
-    TN acc = P[pl.eb3];
-    for (int x = 0; x < DX; ++x) acc += maybe_bf16(S[wl * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
-    jval[w0 + wl] = (double)acc;
+    for (int lay = 0; lay < 2; ++lay) {
+      gemm_mfma<TN>(S, LDX, nwb, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, U, LDX, false, bf16);
+      __syncthreads();
+      for (int q = threadIdx.x; q < nwb * DX; q += blockDim.x) {
+        int wl = q / DX, x = q % DX;
+        TN u = U[wl * LDX + x] + P[(lay == 0 ? pl.eb1 : pl.eb2) + x];
+        TN sg = sigmoid_d(u);
+        ecoef[((w0 + wl) * 2 + lay) * 2 * DX + x] = sg;
+        ecoef[((w0 + wl) * 2 + lay) * 2 * DX + DX + x] = sg * (TN(1) - sg);
+        S[wl * LDX + x] = ssp(u);
+      }
+      __syncthreads();
+    }
+    for (int wl = threadIdx.x; wl < nwb; wl += blockDim.x) {
+      TN acc = P[pl.eb3];
+      for (int x = 0; x < DX; ++x) acc += maybe_bf16(S[wl * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+      jval[w0 + wl] = (double)acc;
+    }
   }
   __syncthreads();
+  if (d.flags & PN_NET_NO_BACKFLOW) {
+    for (int q = threadIdx.x; q < R * M; q += blockDim.x) fval[(w0 + q / (N * M)) * N * M + q % (N * M)] = 1.0;
+    return;
+  }
   // ---- backflow head, per electron row ----
   gemm_mfma<TN>(X, LDX, R, DX, P + pl.kW1, DX, H, LDW, false, bf16);
   __syncthreads();

@@ -154,7 +154,10 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent_adj(
         XS[(q / DX) * LDX + q % DX] = xs_base[(size_t)(L - 1) * R * DX + q];
       __syncthreads();
       // ================= Jastrow head, rows = columns =================
-      {
+      if (d.flags & PN_NET_NO_JASTROW) {
+        for (int q = threadIdx.x; q < R * DX; q += blockDim.x) CX[(q / DX) * LDX + q % DX] = 0;
+        __syncthreads();
+      } else {
         TN* S0 = U;
         TN* E1 = S0 + C * LDX;
         TN* A1 = E1 + C * LDX;
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_net_tangent_adj(
         __syncthreads();
       }
       // ================= backflow head, rows = (electron, column) =================
-      {
+      if (!(d.flags & PN_NET_NO_BACKFLOW)) {
         TN* B1 = U;
         TN* B2 = B1 + R * LDX;
         TN* B3 = B2 + R * LDX;

@@ -329,77 +329,85 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
     copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V);
     copy16(reinterpret_cast<uint4*>(wvs + 4 * N * DX), reinterpret_cast<const uint4*>(ecoef + w * 4 * DX), 4 * DX / V);
   }
-  // ---- Jastrow head on sum_i x_i, rows = columns ----
-  TN* S0 = ES;             // [C][LDX]
-  TN* S1 = ES + C * LDX;   // [C][LDX]
-  for (int q = threadIdx.x; q < C * DX; q += blockDim.x) {
-    const int col = q / DX, x = q % DX;
-    TN s = 0;
-    for (int i = 0; i < N; ++i) s += XT[((size_t)i * C + col) * LDX + x];
-    S0[col * LDX + x] = s;
-  }
-  __syncthreads();
-  for (int lay = 0; lay < 2; ++lay) {
-    TN* Sin = lay == 0 ? S0 : S1;
-    TN* Sout = lay == 0 ? S1 : S0;
-    gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
-    __syncthreads();
-    const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
-    for (int x = threadIdx.x; x < DX; x += blockDim.x) {
-      const TN s1 = ec[x], s2 = ec[DX + x];
-      TN sq = 0;
-#pragma unroll
-      for (int col = 0; col < LC; ++col) {
-        const TN v = Sout[col * LDX + x];
-        sq += v * v;
-        Sout[col * LDX + x] = s1 * v;
-      }
-      Sout[LC * LDX + x] = s1 * Sout[LC * LDX + x] + s2 * sq;
-    }
-    __syncthreads();
-  }
+  // ---- Jastrow head on sum_i x_i, rows = columns (J = 0 without it) ----
   double* jt = jtan + ((int64_t)w * n_chunks + chunk) * C;
-  {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
-      TN acc = 0;
-      for (int x = lane; x < DX; x += 64)
-        acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (lane == 0) jt[col] = (double)acc;
-    }
-  }
-  // ---- backflow head ----
-  gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
-  __syncthreads();
-  for (int lay = 0; lay < 2; ++lay) {
-    TN* A = lay == 0 ? KT : XT;
-    const TN* kc = hstage ? wvs + lay * 2 * N * DX : kcoef + (w * 2 + lay) * 2 * N * DX;
-    for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
-      const int i = q / DX, x = q % DX;
-      const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
-      TN sq = 0;
-      TN* ai = A + (size_t)i * C * LDX + x;
-#pragma unroll
-      for (int col = 0; col < LC; ++col) {
-        const TN v = ai[col * LDX];
-        sq += v * v;
-        ai[col * LDX] = s1 * v;
-      }
-      ai[LC * LDX] = s1 * ai[LC * LDX] + s2 * sq;
+  if (d.flags & PN_NET_NO_JASTROW) {
+    for (int col = threadIdx.x; col < C; col += blockDim.x) jt[col] = 0.0;
+  } else {
+    TN* S0 = ES;             // [C][LDX]
+    TN* S1 = ES + C * LDX;   // [C][LDX]
+    for (int q = threadIdx.x; q < C * DX; q += blockDim.x) {
+      const int col = q / DX, x = q % DX;
+      TN s = 0;
+      for (int i = 0; i < N; ++i) s += XT[((size_t)i * C + col) * LDX + x];
+      S0[col * LDX + x] = s;
     }
     __syncthreads();
-    if (lay == 0) {
-      gemm_mfma<TN>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+    for (int lay = 0; lay < 2; ++lay) {
+      TN* Sin = lay == 0 ? S0 : S1;
+      TN* Sout = lay == 0 ? S1 : S0;
+      gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
+      __syncthreads();
+      const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
+      for (int x = threadIdx.x; x < DX; x += blockDim.x) {
+        const TN s1 = ec[x], s2 = ec[DX + x];
+        TN sq = 0;
+#pragma unroll
+        for (int col = 0; col < LC; ++col) {
+          const TN v = Sout[col * LDX + x];
+          sq += v * v;
+          Sout[col * LDX + x] = s1 * v;
+        }
+        Sout[LC * LDX + x] = s1 * Sout[LC * LDX + x] + s2 * sq;
+      }
       __syncthreads();
     }
+    {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
+        TN acc = 0;
+        for (int x = lane; x < DX; x += 64)
+          acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) jt[col] = (double)acc;
+      }
+    }
   }
-  gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
-  __syncthreads();
+  // ---- backflow head (f = 1, no tangents, without it) ----
   double* ft = ftan + ((int64_t)w * n_chunks + chunk) * N * C * M;
-  for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
-    const int row = q / M, mu = q % M;
-    ft[(int64_t)row * M + mu] = (double)KT[(size_t)row * LDX + mu];
+  if (d.flags & PN_NET_NO_BACKFLOW) {
+    for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
+  } else {
+    gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
+    __syncthreads();
+    for (int lay = 0; lay < 2; ++lay) {
+      TN* A = lay == 0 ? KT : XT;
+      const TN* kc = hstage ? wvs + lay * 2 * N * DX : kcoef + (w * 2 + lay) * 2 * N * DX;
+      for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
+        const int i = q / DX, x = q % DX;
+        const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
+        TN sq = 0;
+        TN* ai = A + (size_t)i * C * LDX + x;
+#pragma unroll
+        for (int col = 0; col < LC; ++col) {
+          const TN v = ai[col * LDX];
+          sq += v * v;
+          ai[col * LDX] = s1 * v;
+        }
+        ai[LC * LDX] = s1 * ai[LC * LDX] + s2 * sq;
+      }
+      __syncthreads();
+      if (lay == 0) {
+        gemm_mfma<TN>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+        __syncthreads();
+      }
+    }
+    gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+    __syncthreads();
+    for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
+      const int row = q / M, mu = q % M;
+      ft[(int64_t)row * M + mu] = (double)KT[(size_t)row * LDX + mu];
+    }
   }
 }
 

@@ -362,6 +362,7 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
       sys->n_up < 0 || sys->n_down < 0 || sys->n_up + sys->n_down < 1 || (sys->n_up > 0 && !sys->det_up) ||
       (sys->n_down > 0 && !sys->det_down) || !(sys->cusp_radius >= 0))
     return PN_ERR_INVALID_ARG;
+  if (net->flags & ~(PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) return PN_ERR_INVALID_ARG;
   if (net->n_feat < 1 || net->dim_x < 1 || net->dim_z < 1 || net->n_layers < 1 || !(net->feat_cutoff > 0))
     return PN_ERR_INVALID_ARG;
   const int N = sys->n_up + sys->n_down;
@@ -400,6 +401,7 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   d.DX = net->dim_x;
   d.DZ = net->dim_z;
   d.L = net->n_layers;
+  d.flags = net->flags;
   d.n_ee = N * (N - 1) / 2;
   d.n_pairs = d.n_ee + N * NN;
   d.n_shell = sys->n_shell;
@@ -664,6 +666,7 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
   char* base = static_cast<char*>(ws);
   const bool derivs = grad || lap || eloc;
   const Dims& d = c->d;
+  const bool no_net = (d.flags & (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) == (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW);
   const void* P = params;
   StageClock clk(c, s);
   if (!fp64) {
@@ -678,7 +681,11 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
     clk.begin(1);
     launch_geometry_orbitals(c, s, n, rt, base, L);
     clk.end(1);
-    if (fp64) {
+    if (no_net) {
+      // neither Jastrow factor nor backflow: f = 1, J = 0 and no network work
+      launch_fill(s, n * d.N * d.M, reinterpret_cast<double*>(base + L.fval), 1.0);
+      launch_fill(s, n, reinterpret_cast<double*>(base + L.jval), 0.0);
+    } else if (fp64) {
       clk.begin(2);
       launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
       clk.end(2);
@@ -698,10 +705,14 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
     clk.end(4);
     if (derivs) {
       clk.begin(5);
-      if (fp64)
+      if (no_net) {
+        launch_fill(s, n * L.n_chunks * d.N * (L.T + 1) * d.M, reinterpret_cast<double*>(base + L.ftan), 0.0);
+        launch_fill(s, n * L.n_chunks * (L.T + 1), reinterpret_cast<double*>(base + L.jtan), 0.0);
+      } else if (fp64) {
         launch_net_tangent<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
-      else
+      } else {
         launch_net_tangent<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      }
       clk.end(5);
       double* g = grad ? grad + w0 * d.N * 3 : reinterpret_cast<double*>(base + L.adj);
       clk.begin(6);
@@ -725,6 +736,8 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
   if (!r || !params || !grad_params || !ws) return PN_ERR_INVALID_ARG;
   const bool full = ct_grad || ct_lap || ct_eloc;
   if (!full && !ct_logabs) return PN_OK;  // every cotangent is zero
+  if ((c->d.flags & (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) == (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW))
+    return PN_OK;  // without both heads psi does not depend on the parameters
   const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
   if (!backward_supported(c, !fp64)) return PN_ERR_UNSUPPORTED_SHAPE;
   WsLayout L = plan(c, nw, prec, full ? kPlanFullAdjoint : kPlanValueAdjoint);

@@ -38,6 +38,7 @@ struct Dims {
   double feat_rc;
   double cusp_rc;
   double v_nn;   // nuclear repulsion, a constant of the geometry
+  int flags;     // PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW
 };
 
 // Device-resident copies of the system tables (owned by the context).
@@ -194,6 +195,7 @@ void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const
                      double* lap, double* eloc);
 void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst);
 void launch_fill0(hipStream_t s, int64_t n, double* dst);
+void launch_fill(hipStream_t s, int64_t n, double* dst, double v);
 void launch_adj_det(const pn_ctx* c, hipStream_t s, int64_t nw, const WsLayout& L, char* ws, const double* ct_logabs,
                     const double* ct_grad, const double* ct_lap, const double* ct_eloc);
 template <typename TN>

@@ -77,6 +77,7 @@ class NetShape:
     dim_x: int  # D_x
     dim_z: int  # D_z
     n_layers: int  # L
+    flags: int = 0  # ansatz variant: 1 = no Jastrow factor, 2 = no backflow
 
 
 @dataclasses.dataclass

@@ -9,6 +9,7 @@ known-answer vectors.
 """
 
 import copy
+import dataclasses
 import math
 import os
 
@@ -732,3 +733,42 @@ def test_langevin_drift_clipped_below_nearest_nucleus():
     d = clipped_drift(r, g, nuc, 0.1)
     assert torch.allclose(torch.linalg.norm(d[0, 0]), torch.tensor(0.1, dtype=torch.float64))  # clipped to 0.1
     assert torch.allclose(d[0, 1], 0.1 * g[0, 1])  # short drift untouched
+
+
+# ------------------------------------------------------- ansatz variants ----
+def test_variant_without_network_is_textbook():
+    """Neither Jastrow factor nor backflow (flags 3): the textbook
+    multideterminant Slater wavefunction times exp(gamma), checked like P2
+    against numpy slogdet and Jacobi-formula derivatives, with the seeded
+    (non-zero) heads left in the parameter blob."""
+    w = _small(2, B=5)
+    sysm = copy.deepcopy(w.system)
+    sysm.cusp_radius = 0.0
+    net = dataclasses.replace(w.net, flags=3)
+    out = Oracle(sysm, net, w.params).evaluate(w.walkers)
+    la, sg, gr, lp, el = _textbook_numpy(sysm, w.walkers, sysm.ci)
+    np.testing.assert_allclose(out["logabs"].numpy(), la, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out["grad"].numpy(), gr, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(out["eloc"].numpy(), el, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("flags,zeroed", [(1, "eta"), (2, "kappa")])
+def test_variant_removes_one_head(flags, zeroed):
+    """Removing a head equals zeroing its last layer (J = 0 or f = 1), and its
+    parameters get exactly zero gradient."""
+    w = _small(2, B=4)
+    s, net = w.system, w.net
+    p = torch.tensor(w.params.copy())
+    P = Params(p, s.n_nuc, s.n_mo, net)
+    head = P.eta if zeroed == "eta" else P.kappa
+    with torch.no_grad():
+        head[4].zero_()
+        head[5].zero_()
+    a = Oracle(s, dataclasses.replace(net, flags=flags), w.params).evaluate(w.walkers)
+    b = Oracle(s, net, P.flat.numpy()).evaluate(w.walkers)
+    for k in ("logabs", "grad", "lap", "eloc"):
+        np.testing.assert_allclose(a[k].numpy(), b[k].numpy(), rtol=1e-12, atol=1e-12)
+    g = Oracle(s, dataclasses.replace(net, flags=flags), w.params).param_grad_logabs(w.walkers, np.ones(4))
+    Pg = Params(g, s.n_nuc, s.n_mo, net)
+    hg = Pg.eta if zeroed == "eta" else Pg.kappa
+    assert all(float(t.abs().max()) == 0.0 for t in hg)
