@@ -70,9 +70,9 @@ class Oracle:
         self.p = Params(flat, self.R.shape[0], self.system.n_mo, self.net)
 
     # -- pieces --------------------------------------------------------------
-    def slater_logdets(self, r, f):
+    def slater_logdets(self, r, f, cusp_s0=None):
         """Per determinant and spin: (sign, ln|det|) of A_p^sigma."""
-        phi = self.orbitals(r)  # [B, N, M]
+        phi = self.orbitals(r, cusp_s0)  # [B, N, M]
         phit = phi * f
         out = []
         for sl, dets in ((slice(0, self.n_up), self.det_up),
@@ -88,8 +88,9 @@ class Oracle:
             out.append((s, l))
         return out
 
-    def log_psi(self, r, params=None):
-        """(ln|psi| [B], sign [B]) for r [B, N, 3]."""
+    def log_psi(self, r, params=None, cusp_s0=None):
+        """(ln|psi| [B], sign [B]) for r [B, N, 3]; cusp_s0 optionally
+        replaces the orbital values at the nuclei of the cusp correction."""
         if params is not None:
             p = Params(params, self.R.shape[0], self.system.n_mo, self.net)
         else:
@@ -106,7 +107,7 @@ class Oracle:
                 J = 0.0 * J
             if flags & 2:  # variant without backflow: f = 1
                 f = 1.0 + 0.0 * f
-        (su, lu), (sd, ld) = self.slater_logdets(r, f)
+        (su, lu), (sd, ld) = self.slater_logdets(r, f, cusp_s0)
         lc = torch.log(torch.abs(self.ci))
         l_p = lc + lu + ld
         s_p = torch.sign(self.ci) * su * sd
@@ -159,6 +160,17 @@ class Oracle:
             return torch.zeros_like(th)
         (gth,) = torch.autograd.grad(loss, th)
         return gth
+
+    def cusp_value_grad(self, r, cotangent):
+        """sum_w cotangent_w d ln|psi_w| / d s0[I, mu] for the orbital values
+        at the nuclei of the cusp correction (Methods, "Cusp conditions": the
+        paper optimizes them); zero for pairs that are not corrected."""
+        r = torch.as_tensor(r, dtype=torch.float64)
+        s0 = self.orbitals.s0.detach().clone().requires_grad_(True)
+        lp, _ = self.log_psi(r, cusp_s0=s0)
+        (g,) = torch.autograd.grad((lp * torch.as_tensor(cotangent, dtype=torch.float64)).sum(), s0,
+                                   allow_unused=True)
+        return torch.zeros_like(s0) if g is None else g
 
     def param_grad_logabs(self, r, cotangent):
         """sum_w cotangent_w * d ln|psi_w| / d theta (value-path adjoint)."""

@@ -95,6 +95,7 @@ class CuspCorrectedOrbitals:
         return sum(cn * torch.exp(-a * rho**2) for a, cn in terms)
 
     def _setup(self, nuc_val):
+        self.s0 = torch.zeros(self.R.shape[0], self.n_mo, dtype=torch.float64)
         for I in range(self.R.shape[0]):
             phi_at_nuc = self.uncorrected(self.R[I][None])[0]  # [n_mo]
             for mu in range(self.n_mo):
@@ -103,6 +104,7 @@ class CuspCorrectedOrbitals:
                     continue
                 s_at0 = float(self._s_radial(terms, torch.zeros((), dtype=torch.float64)))
                 s0 = s_at0 if nuc_val is None else float(nuc_val[I, mu])
+                self.s0[I, mu] = s0
                 eta0 = float(phi_at_nuc[mu]) - s_at0
                 # value, slope and curvature of s at r_cusp by autograd
                 rho = torch.tensor(self.rc, dtype=torch.float64, requires_grad=True)
@@ -112,30 +114,39 @@ class CuspCorrectedOrbitals:
                 s, ds, d2s = float(s.detach()), float(ds.detach()), float(d2s)
                 if s0 == 0.0 or s * s0 <= 0.0:
                     continue
-                a0 = math.log(abs(s0))
-                a1 = -float(self.Z[I]) * (eta0 + s0) / s0
                 X1, X2 = math.log(abs(s)), ds / s
                 X3 = d2s / s - X2**2
-                rc = self.rc
-                M = torch.tensor([[rc**2, rc**3, rc**4],
-                                  [2 * rc, 3 * rc**2, 4 * rc**3],
-                                  [2.0, 6 * rc, 12 * rc**2]], dtype=torch.float64)
-                rhs = torch.tensor([X1 - a0 - a1 * rc, X2 - a1, X3], dtype=torch.float64)
-                a234 = torch.linalg.solve(M, rhs)
-                alpha = [a0, a1] + [float(v) for v in a234]
-                self.corr.append((I, mu, math.copysign(1.0, s0), alpha, terms))
+                self.corr.append((I, mu, math.copysign(1.0, s0), (eta0, X1, X2, X3), terms))
+
+    def _alpha(self, I, mu, s0, fit):
+        """Coefficients a0..a4 of the corrected s part for nucleus value s0
+        (a torch scalar, so that they can be differentiated in s0)."""
+        eta0, X1, X2, X3 = fit
+        rc = self.rc
+        a0 = torch.log(torch.abs(s0))
+        a1 = -float(self.Z[I]) * (eta0 + s0) / s0
+        M = torch.tensor([[rc**2, rc**3, rc**4],
+                          [2 * rc, 3 * rc**2, 4 * rc**3],
+                          [2.0, 6 * rc, 12 * rc**2]], dtype=torch.float64)
+        rhs = torch.stack([X1 - a0 - a1 * rc, X2 - a1, torch.zeros_like(a0) + X3])
+        a234 = torch.linalg.solve(M, rhs)
+        return [a0, a1, a234[0], a234[1], a234[2]]
 
     def uncorrected(self, r: torch.Tensor):
         chi = gto_basis(r, self.R, self.sc, self.sl, self.se)
         return chi @ self.C
 
-    def __call__(self, r: torch.Tensor):
-        """r: [B, N, 3] -> phi [B, N, n_mo]."""
+    def __call__(self, r: torch.Tensor, s0=None):
+        """r: [B, N, 3] -> phi [B, N, n_mo].  s0 [n_nuc, n_mo] (optional,
+        may require grad) replaces the nucleus values of the corrected
+        pairs; which pairs are corrected is fixed at set-up."""
         phi = self.uncorrected(r)
         if not self.corr:
             return phi
+        s0 = self.s0 if s0 is None else s0
         cols = [phi[..., mu] for mu in range(self.n_mo)]
-        for I, mu, sgn, alpha, terms in self.corr:
+        for I, mu, sgn, fit, terms in self.corr:
+            alpha = self._alpha(I, mu, s0[I, mu], fit)
             rho = torch.sqrt(((r - self.R[I]) ** 2).sum(-1))
             inside = rho < self.rc
             rho_c = torch.where(inside, rho, torch.full_like(rho, self.rc))

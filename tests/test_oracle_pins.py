@@ -772,3 +772,37 @@ def test_variant_removes_one_head(flags, zeroed):
     Pg = Params(g, s.n_nuc, s.n_mo, net)
     hg = Pg.eta if zeroed == "eta" else Pg.kappa
     assert all(float(t.abs().max()) == 0.0 for t in hg)
+
+
+def test_cusp_value_gradient_finite_differences():
+    """d ln|psi| / d s0 (orbital values at the nucleus, variational in the
+    paper) against central differences of ln|psi| with the nucleus values
+    passed through the system description, for walkers with electrons inside
+    the cusp radius."""
+    w = _small(2, B=4)
+    o = Oracle(w.system, w.net, w.params)
+    r = w.walkers.copy()
+    u = np.array([0.6, -0.48, 0.64])
+    r[0, 0] = w.system.nuc_xyz[0] + 0.05 * u
+    r[1, 3] = w.system.nuc_xyz[0] + 0.02 * u[::-1]
+    r[2, 7] = w.system.nuc_xyz[0] + 0.08 * u
+    ct = np.array([1.0, -0.6, 0.8, 0.3])
+    g = o.cusp_value_grad(r, ct).numpy()
+    s0 = o.orbitals.s0.numpy().copy()
+    corrected = [(I, mu) for I, mu, *_ in o.orbitals.corr]
+    assert corrected
+    nz = 0
+    for I, mu in corrected[:6]:
+        h = 1e-6 * max(1.0, abs(s0[I, mu]))
+        vals = []
+        for sgn in (1, -1):
+            sysm = copy.deepcopy(w.system)
+            sv = s0.copy()
+            sv[I, mu] += sgn * h
+            sysm.cusp_nuc_value = sv
+            lp, _ = Oracle(sysm, w.net, w.params).log_psi(torch.tensor(r))
+            vals.append(float((torch.tensor(ct) * lp).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[I, mu]) <= 1e-6 * max(1.0, abs(fd)), (I, mu, fd, g[I, mu])
+        nz += abs(fd) > 1e-6
+    assert nz > 0  # the walkers do probe the corrected region
