@@ -195,6 +195,20 @@ pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walk
                            const double* ct_logabs, const double* ct_grad, const double* ct_lap,
                            const double* ct_eloc, double* grad_params, void* ws, size_t ws_bytes);
 
+/* Gradient in the orbital values at the nuclei (Methods, "Cusp conditions":
+ * the corrected on-centre s part of each MO takes the value s0 at the
+ * nucleus, which the paper optimizes; s0 is the cusp_nuc_value of the system
+ * description, or its default):
+ *   grad_cusp[I][mu] += sum_w ct_logabs[w] d ln|psi_w| / d s0[I][mu]
+ * grad_cusp is [n_nuc][n_mo] FP64, accumulated into; entries of pairs
+ * without correction stay unchanged.  Only electrons inside the cusp radius
+ * of a nucleus contribute.  The forward values are recomputed (workspace of
+ * pn_workspace_bytes); the sum has a fixed order.  To train s0, create the
+ * context again with the new values (the context is immutable). */
+pn_status pn_eval_backward_cusp(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers,
+                                const double* r, const double* params, pn_precision prec,
+                                const double* ct_logabs, double* grad_cusp, void* ws, size_t ws_bytes);
+
 /* ---- Langevin Monte Carlo sampling ----------------------------------------
  * Methods, "Ansatz optimization" (Table 2: target acceptance 57 %, 50
  * discarded steps, 1 decorrelation step, resampling every 100 iterations):

@@ -122,6 +122,8 @@ def load_library():
     lib.pn_eval.restype = i32
     lib.pn_param_layout.argtypes = [vp, ctypes.POINTER(pn_param_entry), i32, ctypes.POINTER(i32)]
     lib.pn_param_layout.restype = i32
+    lib.pn_eval_backward_cusp.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, ctypes.c_size_t]
+    lib.pn_eval_backward_cusp.restype = i32
     lib.pn_workspace_bytes_full.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pn_workspace_bytes_full.restype = i32
     lib.pn_eval_backward.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
@@ -196,6 +198,7 @@ class PauliNetContext:
         self._ctx = out
         self._lib = lib
         self.n_elec = s.n_up + s.n_down
+        self.n_nuc, self.n_mo = int(s.n_nuc), int(s.n_mo)
         self._ws = {}
 
     def close(self):
@@ -318,6 +321,27 @@ class PauliNetContext:
                                         _ptr(grad_params), _ptr(ws), ws.numel())
         _check(st, "pn_eval_backward")
         return grad_params
+
+
+def _cusp_grad(self, r, params, ct_logabs, prec=PN_PREC_FP64, grad_cusp=None, ws=None):
+    """grad_cusp[I, mu] += sum_w ct_logabs[w] d ln|psi_w| / d s0[I, mu] (the
+    orbital values at the nuclei of the cusp correction)."""
+    import torch
+    r = r.contiguous()
+    params = params.contiguous()
+    ct_logabs = ct_logabs.to(torch.float64).contiguous()
+    B = int(r.shape[0])
+    if grad_cusp is None:
+        grad_cusp = torch.zeros(self.n_nuc, self.n_mo, dtype=torch.float64, device=r.device)
+    if ws is None:
+        ws = self.workspace(B, prec, r.device)
+    _check(self._lib.pn_eval_backward_cusp(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
+                                           _ptr(ct_logabs), _ptr(grad_cusp), _ptr(ws), ws.numel()),
+           "pn_eval_backward_cusp")
+    return grad_cusp
+
+
+PauliNetContext.eval_backward_cusp = _cusp_grad
 
 
 def _autograd_function():

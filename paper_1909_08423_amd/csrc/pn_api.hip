@@ -452,7 +452,8 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   s_first[NN] = (int)s_basis.size();
   // nuclear cusp polynomials (Ma et al. scheme, nucleus value as input)
   std::vector<int> cusp_on((size_t)NN * M, 0);
-  std::vector<double> cusp_sign((size_t)NN * M, 0.0), cusp_alpha((size_t)NN * M * 5, 0.0);
+  std::vector<double> cusp_sign((size_t)NN * M, 0.0), cusp_alpha((size_t)NN * M * 5, 0.0),
+      cusp_dalpha((size_t)NN * M * 5, 0.0);
   int n_on = 0;
   if (d.cusp_rc > 0) {
     const double rc = d.cusp_rc;
@@ -490,6 +491,9 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
         double Mm[3][3] = {{rc * rc, rc * rc * rc, rc * rc * rc * rc},
                            {2 * rc, 3 * rc * rc, 4 * rc * rc * rc},
                            {2.0, 6 * rc, 12 * rc * rc}};
+        double Md[3][3];  // solve3 eliminates in place: keep a copy for the derivative system
+        for (int a = 0; a < 3; ++a)
+          for (int b2 = 0; b2 < 3; ++b2) Md[a][b2] = Mm[a][b2];
         double rhs[3] = {X1 - a0 - a1 * rc, X2 - a1, X3}, sol[3];
         if (!solve3(Mm, rhs, sol)) continue;
         size_t q = (size_t)I * M + mu;
@@ -500,6 +504,15 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
         cusp_alpha[5 * q + 2] = sol[0];
         cusp_alpha[5 * q + 3] = sol[1];
         cusp_alpha[5 * q + 4] = sol[2];
+        // d alpha / d s0: a0 = ln|s0|, a1 = -Z (eta0 + s0) / s0, a2..a4 from the
+        // linear system whose right-hand side depends on a0 and a1
+        const double da0 = 1.0 / s0, da1 = sys->charge[I] * eta0 / (s0 * s0);
+        double rhs_d[3] = {-da0 - da1 * rc, -da1, 0.0}, sol_d[3];
+        if (solve3(Md, rhs_d, sol_d)) {
+          cusp_dalpha[5 * q + 0] = da0;
+          cusp_dalpha[5 * q + 1] = da1;
+          for (int k = 0; k < 3; ++k) cusp_dalpha[5 * q + 2 + k] = sol_d[k];
+        }
         ++n_on;
       }
     }
@@ -544,6 +557,7 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   t.cusp_on = dev_copy(cusp_on, &err);
   t.cusp_sign = dev_copy(cusp_sign, &err);
   t.cusp_alpha = dev_copy(cusp_alpha, &err);
+  t.cusp_dalpha = dev_copy(cusp_dalpha, &err);
   t.s_first = dev_copy(s_first, &err);
   t.s_basis = dev_copy(s_basis, &err);
   t.s_exp = dev_copy(s_exp, &err);
@@ -571,7 +585,7 @@ void pn_ctx_destroy(pn_ctx* c) {
   }
   void* ptrs[] = {c->t.nuc_xyz, c->t.charge, c->t.shell_center, c->t.shell_l, c->t.shell_exp, c->t.shell_norm,
                   c->t.shell_first, c->t.mo, c->t.det_up, c->t.det_dn, c->t.ci_log, c->t.ci_sign, c->t.cusp_on,
-                  c->t.cusp_sign, c->t.cusp_alpha, c->t.s_first, c->t.s_basis, c->t.s_exp, c->t.s_norm,
+                  c->t.cusp_sign, c->t.cusp_alpha, c->t.cusp_dalpha, c->t.s_first, c->t.s_basis, c->t.s_exp, c->t.s_norm,
                   c->t.feat_mu, c->t.feat_sig2inv, c->t.pair_ij, c->t.pair_index};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -792,6 +806,49 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
       }
     }
     launch_backward(c, s, n, rt, P, !fp64, bf16, ctl, base, L, grad_params, full);
+  }
+  if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
+  return PN_OK;
+}
+
+pn_status pn_eval_backward_cusp(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                                pn_precision prec, const double* ct_logabs, double* grad_cusp, void* ws,
+                                size_t ws_bytes) {
+  if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  if (nw == 0) return PN_OK;
+  if (!r || !params || !ct_logabs || !grad_cusp || !ws) return PN_ERR_INVALID_ARG;
+  if (c->n_cusp_on == 0) return PN_OK;  // no corrected orbital: the gradient is zero
+  const Dims& d = c->d;
+  if (cusp_grad_lds_bytes(d) > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
+  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
+  WsLayout L = plan(c, nw, prec, kPlanValueAdjoint);
+  if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
+  char* base = static_cast<char*>(ws);
+  const void* P = params;
+  if (!fp64) {
+    launch_convert_params(s, c->pl.total, params, reinterpret_cast<float*>(base + L.params_net));
+    P = base + L.params_net;
+  }
+  const bool no_net = (d.flags & (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) == (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW);
+  double* la = reinterpret_cast<double*>(base + L.adj);
+  double* sg = la + L.tile;
+  double* slot = reinterpret_cast<double*>(base + L.gpart);  // per-block partial sums
+  for (int64_t w0 = 0; w0 < nw; w0 += L.tile) {
+    const int64_t n = std::min<int64_t>(L.tile, nw - w0);
+    const double* rt = r + w0 * d.N * 3;
+    launch_geometry_orbitals(c, s, n, rt, base, L);
+    if (no_net) {
+      launch_fill(s, n * d.N * d.M, reinterpret_cast<double*>(base + L.fval), 1.0);
+      launch_fill(s, n, reinterpret_cast<double*>(base + L.jval), 0.0);
+    } else if (fp64) {
+      launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
+      launch_net_value<double>(c, s, n, static_cast<const double*>(P), base, L, false);
+    } else {
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+    }
+    launch_slater_value(c, s, n, base, L, la, sg);
+    launch_cusp_grad(c, s, n, rt, base, L, ct_logabs + w0, slot, grad_cusp);
   }
   if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
   return PN_OK;

@@ -59,6 +59,7 @@ struct DevTables {
   int* cusp_on;        // [NN][M]
   double* cusp_sign;   // [NN][M]
   double* cusp_alpha;  // [NN][M][5]
+  double* cusp_dalpha; // [NN][M][5] derivatives of the coefficients in the nucleus value
   int* s_first;        // [NN+1] CSR offsets into s_basis
   int* s_basis;        // basis index of each s function, grouped by nucleus
   double* s_exp;       // exponent of each s function (same order)
@@ -196,6 +197,9 @@ void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const
 void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst);
 void launch_fill0(hipStream_t s, int64_t n, double* dst);
 void launch_fill(hipStream_t s, int64_t n, double* dst, double v);
+size_t cusp_grad_lds_bytes(const Dims& d);
+void launch_cusp_grad(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws, const WsLayout& L,
+                      const double* ct, double* slot, double* grad);
 void launch_adj_det(const pn_ctx* c, hipStream_t s, int64_t nw, const WsLayout& L, char* ws, const double* ct_logabs,
                     const double* ct_grad, const double* ct_lap, const double* ct_eloc);
 template <typename TN>

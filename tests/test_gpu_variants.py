@@ -98,3 +98,26 @@ def test_variant_without_network_has_no_parameter_gradient(pn):
                           ct_eloc=torch.ones(4, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     assert float(g.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("idx", [2, 3])
+def test_cusp_value_gradient_matches_oracle(pn, idx):
+    """d ln|psi| / d s0 (orbital values at the nuclei) for walkers with
+    electrons inside the cusp radius, FP64, against the oracle's autograd
+    gradient (itself pinned by finite differences)."""
+    w = make_config(idx, n_walkers=5)
+    r = w.walkers.copy()
+    u = np.array([0.6, -0.48, 0.64])
+    nuc = w.system.nuc_xyz
+    r[0, 0] = nuc[0] + 0.05 * u
+    r[1, 3] = nuc[-1] + 0.02 * u[::-1]
+    r[2, 1] = nuc[0] + 0.08 * u
+    r[3, 4] = nuc[len(nuc) // 2] + 0.03 * u
+    ct = np.array([1.0, -0.6, 0.8, 0.3, 1.2])
+    announce(f"cusp value gradient workload {idx}")
+    ref = Oracle(w.system, w.net, w.params).cusp_value_grad(r, ct).numpy()
+    ctx = pn.PauliNetContext(w.system, w.net)
+    g = ctx.eval_backward_cusp(torch.tensor(r, device="cuda"), torch.tensor(w.params, device="cuda"),
+                               torch.tensor(ct, device="cuda"), pn.PN_PREC_FP64).cpu().numpy()
+    assert np.abs(ref).max() > 0
+    assert np.linalg.norm(g - ref) <= 1e-8 * np.linalg.norm(ref), (np.abs(g - ref).max(), np.abs(ref).max())
