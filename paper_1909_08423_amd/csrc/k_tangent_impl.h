@@ -192,10 +192,14 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0;
         if (n > 0) {
+          // j = i contributes w = 0 (no branch, so consecutive partners'
+          // loads can overlap)
+#pragma unroll 2
           for (int j = j_lo; j < j_hi; ++j) {
-            if (j == i) continue;
-            const TN wv = STAGE ? wvs[pidx[i * N + j] * DZ + z] : fv[(int64_t)pidx[i * N + j] * DZ + z];
-            const TN* hj = HT + (size_t)j * C * LDZ + z;
+            const int pp = max(pidx[i * N + j], 0);
+            const TN wv0 = STAGE ? wvs[pp * DZ + z] : fv[(int64_t)pp * DZ + z];
+            const TN wv = j == i ? TN(0) : wv0;
+            const TN* hj = HT + j * C * LDZ + z;
 #pragma unroll
             for (int c = 0; c < C; ++c) acc[c] += wv * hj[c * LDZ];
           }

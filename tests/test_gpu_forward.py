@@ -52,10 +52,12 @@ def test_fp64_parity_ragged_batch(pn, idx):
         assert v.max() <= TOL64, f"{k}: worst {v.max():.3e} at walker {int(v.argmax())}; {summarize(rat)}"
 
 
-@pytest.mark.parametrize("idx", [1, 2, 3])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5])
 def test_fp64_parity_full_batch_sample(pn, idx):
     """Full-size batch in the benchmark's launch configuration; the oracle
-    values of a sample of walkers are compared one by one."""
+    values of a sample of walkers are compared one by one.  The 30-electron
+    batch (16384 walkers) is processed in several walker tiles, the sample
+    reaching into the last one."""
     fx = load_fixture(idx)
     w = make_config(idx)
     announce(f"fp64 full batch workload {idx} B={w.walkers.shape[0]}")
@@ -226,3 +228,24 @@ def test_param_layout_matches_blob_order(pn):
     for (name, off, shape), (_, t) in zip(lay, ref):
         assert off == int(t.reshape(-1)[0]), name
         assert shape == tuple(t.shape), name
+
+
+def test_edge_batches(pn):
+    """An empty batch is a no-op; a single walker gives bit for bit what it
+    gets inside a ragged batch (walkers are independent all the way)."""
+    w = make_config(2, n_walkers=67)
+    announce("edge batches, workload 2")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    r0 = torch.zeros(0, w.system.n_elec, 3, dtype=torch.float64, device="cuda")
+    out0 = ctx.eval(r0, th, pn.PN_PREC_FP64)
+    assert out0["eloc"].numel() == 0
+    g = torch.zeros(ctx.param_count, dtype=torch.float64, device="cuda")
+    ctx.eval_backward(r0, th, torch.zeros(0, dtype=torch.float64, device="cuda"), pn.PN_PREC_FP64, grad_params=g)
+    torch.cuda.synchronize()
+    assert float(g.abs().max()) == 0.0
+    full, _ = _run(pn, w, w.walkers, pn.PN_PREC_FP64)
+    for k in (0, 66):
+        one, _ = _run(pn, w, w.walkers[k:k + 1], pn.PN_PREC_FP64)
+        for key in one:
+            np.testing.assert_array_equal(one[key][0], full[key][k])
