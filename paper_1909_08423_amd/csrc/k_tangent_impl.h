@@ -210,34 +210,37 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
         if (i >= e_lo && i <= e_hi) {
           const TN* gi = cg + (size_t)(i - e_lo) * N * 4;  // r_j - r_i
           const int c0 = 3 * i - a0;
+          // the chunk's columns of electron i: masks instead of branches, and
+          // clamped column indices for the (masked) reads
+          const TN m0 = (c0 >= 0 && c0 < Tc) ? TN(1) : TN(0);
+          const TN m1 = (c0 + 1 >= 0 && c0 + 1 < Tc) ? TN(1) : TN(0);
+          const TN m2 = (c0 + 2 >= 0 && c0 + 2 < Tc) ? TN(1) : TN(0);
+          const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
           TN sv0 = 0, sv1 = 0, sv2 = 0;
+          // j = i adds nothing: its staged w'/d, w'' and 1/|r_i - r_j| are zero
+#pragma unroll 2
           for (int j = j_lo; j < j_hi; ++j) {
-            if (j == i) continue;
             TN wd, w2;
             if constexpr (STAGE) {
               wd = wds[((i - e_lo) * NP + j) * DZ + z];
               w2 = w2s[((i - e_lo) * NP + j) * DZ + z];
             } else {
-              const int64_t p = pidx[i * N + j];
-              wd = fd[p * DZ + z];
-              w2 = f2[p * DZ + z];
+              const int64_t p = max(pidx[i * N + j], 0);
+              wd = j == i ? TN(0) : fd[p * DZ + z];
+              w2 = j == i ? TN(0) : f2[p * DZ + z];
             }
             const TN hj = hvs[j * DZ + z];
             const TN inv = gi[4 * j + 3];
-            const TN* hjc = HT + (size_t)j * C * LDZ + z;
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-              const int c = c0 + al;
-              if (c < 0 || c >= Tc) continue;
-              const TN ua = -gi[4 * j + al];  // (r_i - r_j)_alpha
-              const TN ur = ua * inv;
-              const TN dw = wd * ua;
-              if (al == 0) sv0 += dw * hj;
-              if (al == 1) sv1 += dw * hj;
-              if (al == 2) sv2 += dw * hj;
-              lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hj;
-              if (n > 0) lap += TN(2) * dw * hjc[c * LDZ];
-            }
+            const TN* hjc = HT + j * C * LDZ + z;
+            const TN u0 = -gi[4 * j], u1 = -gi[4 * j + 1], u2 = -gi[4 * j + 2];  // (r_i - r_j)_alpha
+            const TN r0 = u0 * inv, r1 = u1 * inv, r2 = u2 * inv;
+            const TN d0 = m0 * wd * u0, d1 = m1 * wd * u1, d2 = m2 * wd * u2;
+            sv0 += d0 * hj;
+            sv1 += d1 * hj;
+            sv2 += d2 * hj;
+            lap += (m0 * (w2 * r0 * r0 + wd * (TN(1) - r0 * r0)) + m1 * (w2 * r1 * r1 + wd * (TN(1) - r1 * r1)) +
+                    m2 * (w2 * r2 * r2 + wd * (TN(1) - r2 * r2))) * hj;
+            if (n > 0) lap += TN(2) * (d0 * hjc[k0 * LDZ] + d1 * hjc[k1 * LDZ] + d2 * hjc[k2 * LDZ]);
           }
 #pragma unroll
           for (int c = 0; c < C; ++c) {
