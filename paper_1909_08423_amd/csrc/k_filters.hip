@@ -60,8 +60,12 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
   }
   __syncthreads();
   // --- feature jets (computed in FP64, stored in the network type) ---
-  for (int q = threadIdx.x; q < rows * K; q += blockDim.x) {
+  for (int q = threadIdx.x; q < PT * K; q += blockDim.x) {
     int row = q / K, k = q % K;
+    if (row >= rows) {  // padding rows of a partial tile: zero features
+      E[(0 * PT + row) * LDK + k] = E[(1 * PT + row) * LDK + k] = E[(2 * PT + row) * LDK + k] = TN(0);
+      continue;
+    }
     double dv = dd[row];
     double dm = dv - t.feat_mu[k], s = t.feat_sig2inv[k];
     double eg = exp(-dv - dm * dm * s);
@@ -72,9 +76,9 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
   }
   __syncthreads();
   const ParamLayout::Layer& Lp = pl.layer[layer];
-  // --- first Linear on the three jets ---
-  for (int jet = 0; jet < 3; ++jet)
-    gemm_mfma<TN>(E + jet * PT * LDK, LDK, rows, K, P + Lp.w1W[ch], DZ, U + jet * PT * LDZ, LDZ, false, bf16);
+  // --- first Linear on the three jets: one product over the 3 PT rows (the
+  // jets are stacked with equal strides; rows past `rows` are zero features) ---
+  gemm_mfma<TN>(E, LDK, 3 * PT, K, P + Lp.w1W[ch], DZ, U, LDZ, false, bf16);
   __syncthreads();
   // --- ssp jets, in place; bias on the value ---
   for (int q = threadIdx.x; q < rows * DZ; q += blockDim.x) {
@@ -90,9 +94,8 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
     u0[2 * PT * LDZ] = sg * u2 + sg * (TN(1) - sg) * up * up;
   }
   __syncthreads();
-  // --- second Linear ---
-  for (int jet = 0; jet < 3; ++jet)
-    gemm_mfma<TN>(U + jet * PT * LDZ, LDZ, rows, DZ, P + Lp.w2W[ch], DZ, O + jet * PT * LDZ, LDZ, false, bf16);
+  // --- second Linear, again over the stacked jets ---
+  gemm_mfma<TN>(U, LDZ, 3 * PT, DZ, P + Lp.w2W[ch], DZ, O, LDZ, false, bf16);
   __syncthreads();
   // --- store as [walker][layer][jet][pair][DZ]; bias on the value ---
   const int64_t lstride = (int64_t)3 * d.n_pairs * DZ;
