@@ -63,7 +63,7 @@ def chunk_T(s, net, prec):
         C = T + 1
         R = N * C
         NCE = min(N, T // 3 + 2)
-        e = N * DZ + R * (LDX + LDHZ) + 2 * C * LDX + NCE * (N + NN) * 4
+        e = N * DZ + R * (LDX + LDHZ) + max(2 * C * LDX, NCE * C * LDZ) + NCE * (N + NN) * 4
         if stage:
             e += n_ee * DZ + 2 * NCE * (N + NN) * DZ
         return 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + e * tn

@@ -16,7 +16,7 @@ size_t tangent_lds_bytes(const Dims& d, int T, bool stage) {
   const int C = T + 1, R = d.N * C;
   const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
   const int NCE = std::min(d.N, T / 3 + 2);  // electrons a chunk of T coordinates can touch
-  size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + 2 * (size_t)C * LDX + (size_t)NCE * (d.N + d.NN) * 4;
+  size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + std::max(2 * (size_t)C * LDX, (size_t)NCE * C * LDZ) + (size_t)NCE * (d.N + d.NN) * 4;
   if (stage) tn += (size_t)d.n_ee * d.DZ + 2 * (size_t)NCE * (d.N + d.NN) * d.DZ;
   return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN);
 }

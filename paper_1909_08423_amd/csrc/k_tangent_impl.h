@@ -23,6 +23,12 @@
 // The values (h, w, w'/d, w'', ssp', ssp'') come from the value pass.  The
 // dense products run on the matrix cores (mfma_gemm.h); the message sums are
 // register-blocked over the C columns, which are a template parameter.
+// Per layer the block passes five barriers: after the staging and the h
+// product, and after each channel's message sums and product.  The nuclear
+// channel's
+// messages (non-zero only in rows of the chunk's own electrons, as the
+// nuclei do not move) are extra items of channel 0's sums, and their product
+// follows channel 0's in the same phase, on the same tile-to-wave map.
 // With STAGE the layer's filter values and the chunk electrons' filter
 // derivatives are copied to LDS first (coalesced), so the message sums read
 // only LDS; without it (systems whose pair tables do not fit) they read the
@@ -100,8 +106,10 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
   TN* HT = XT + R * LDX;                                        // [R][LDZ]  (layers)
   TN* ZT = HT + R * LDZ;                                        // [R][LDZ]  (layers)
   TN* KT = HT;                                                  // [R][LDX]  (backflow head)
-  TN* ES = HT + R * LDHZ;                                       // [2][C][LDX]
-  TN* cg = ES + 2 * C * LDX;                                    // [NCE][N][4]  r_i - r_k, 1/|r_i - r_k|
+  const int nce_max = min(N, T / 3 + 2);                        // chunk electrons, at most
+  TN* ES = HT + R * LDHZ;  // [2][C][LDX] Jastrow head; in the layers [NCE][C][LDZ] nuclear messages
+  TN* ZN = ES;
+  TN* cg = ES + max(2 * C * LDX, nce_max * C * LDZ);            // [NCE][N][4]  r_i - r_k, 1/|r_i - r_k|
   TN* cgn = cg + NCE * N * 4;                                   // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
   const int NP = N + d.NN;                                      // partners of a chunk electron
   TN* wvs = cgn + NCE * d.NN * 4;                               // [n_ee][DZ]      (STAGE) w, all ee pairs
@@ -179,10 +187,47 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
         }
       }
     }
-    if (n > 0) gemm_mfma<TN>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
+    if (n > 0) gemm_mfma<TN, true>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
     __syncthreads();
     for (int ch = 0; ch < 2; ++ch) {
-      for (int q = threadIdx.x; q < N * DZ; q += blockDim.x) {
+      // channel 0 also takes the nuclear messages, which only rows of the
+      // chunk's own electrons have (extra items; their product joins
+      // channel 0's)
+      const int n_items = N * DZ + (ch == 0 ? NCE * DZ : 0);
+      for (int q = threadIdx.x; q < n_items; q += blockDim.x) {
+        if (q >= N * DZ) {
+          const int i = e_lo + (q - N * DZ) / DZ, z = q % DZ;
+          TN* zn = ZN + (size_t)(i - e_lo) * C * LDZ + z;
+          TN acc[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] = 0;
+          const int c0 = 3 * i - a0;
+          for (int I = 0; I < d.NN; ++I) {
+            const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
+            const TN y = P[pl.Y + I * DZ + z];
+            TN wd, w2;
+            if constexpr (STAGE) {
+              wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
+              w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
+            } else {
+              const int64_t p = d.n_ee + i * d.NN + I;
+              wd = fd[p * DZ + z];
+              w2 = f2[p * DZ + z];
+            }
+#pragma unroll
+            for (int c = 0; c < T; ++c) {
+              const int al = c - c0;
+              if (al < 0 || al > 2 || c >= Tc) continue;
+              const TN ua = gn[al];
+              const TN ur = ua * gn[3];
+              acc[c] += wd * ua * y;
+              acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < C; ++c) zn[c * LDZ] = acc[c];
+          continue;
+        }
         const int i = q / DZ, z = q % DZ;
         const bool up_i = i < NU;
         // electrons of this channel: same spin (ch 0) or opposite spin (ch 1)
@@ -192,16 +237,44 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0;
         if (n > 0) {
-          // j = i contributes w = 0 (no branch, so consecutive partners'
-          // loads can overlap)
-#pragma unroll 2
-          for (int j = j_lo; j < j_hi; ++j) {
-            const int pp = max(pidx[i * N + j], 0);
-            const TN wv0 = STAGE ? wvs[pp * DZ + z] : fv[(int64_t)pp * DZ + z];
-            const TN wv = j == i ? TN(0) : wv0;
-            const TN* hj = HT + j * C * LDZ + z;
+          // Two partners per step; j = i contributes w = 0 (no branch).  All
+          // of a step's LDS reads are issued before its first product (the
+          // scheduling barriers keep the compiler from interleaving read,
+          // wait, multiply per column, which would expose one LDS latency
+          // per column).
+          // (wide FP64 chunks take one partner per step: fewer live registers)
+          constexpr bool kTwo = C * sizeof(TN) <= 48;
+          int j = j_lo;
+          for (; kTwo && j + 1 < j_hi; j += 2) {
+            const int pa = max(pidx[i * N + j], 0), pb = max(pidx[i * N + j + 1], 0);
+            const TN* hja = HT + j * C * LDZ + z;
+            const TN* hjb = hja + C * LDZ;
+            TN ha[C], hb[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] += wv * hj[c * LDZ];
+            for (int c = 0; c < C; ++c) ha[c] = hja[c * LDZ];
+#pragma unroll
+            for (int c = 0; c < C; ++c) hb[c] = hjb[c * LDZ];
+            const TN wa0 = STAGE ? wvs[pa * DZ + z] : fv[(int64_t)pa * DZ + z];
+            const TN wb0 = STAGE ? wvs[pb * DZ + z] : fv[(int64_t)pb * DZ + z];
+            __builtin_amdgcn_sched_barrier(0);
+            const TN wa = j == i ? TN(0) : wa0, wb = j + 1 == i ? TN(0) : wb0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wa * ha[c];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wb * hb[c];
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          for (; j < j_hi; ++j) {
+            const int pa = max(pidx[i * N + j], 0);
+            const TN* hja = HT + j * C * LDZ + z;
+            TN ha[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) ha[c] = hja[c * LDZ];
+            const TN wa0 = STAGE ? wvs[pa * DZ + z] : fv[(int64_t)pa * DZ + z];
+            __builtin_amdgcn_sched_barrier(0);
+            const TN wa = j == i ? TN(0) : wa0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wa * ha[c];
           }
         }
         TN* zi = ZT + (size_t)i * C * LDZ + z;
@@ -217,30 +290,56 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
           const TN m2 = (c0 + 2 >= 0 && c0 + 2 < Tc) ? TN(1) : TN(0);
           const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
           TN sv0 = 0, sv1 = 0, sv2 = 0;
-          // j = i adds nothing: its staged w'/d, w'' and 1/|r_i - r_j| are zero
-#pragma unroll 2
-          for (int j = j_lo; j < j_hi; ++j) {
-            TN wd, w2;
+          // j = i adds nothing: its staged w'/d, w'' and 1/|r_i - r_j| are zero.
+          // A partner's reads are issued together (FP32: two partners per step).
+          struct Own {
+            TN wd, w2, hj, g0, g1, g2, inv, h0, h1, h2;
+          };
+          auto load_own = [&](int j) {
+            Own o;
             if constexpr (STAGE) {
-              wd = wds[((i - e_lo) * NP + j) * DZ + z];
-              w2 = w2s[((i - e_lo) * NP + j) * DZ + z];
+              o.wd = wds[((i - e_lo) * NP + j) * DZ + z];
+              o.w2 = w2s[((i - e_lo) * NP + j) * DZ + z];
             } else {
               const int64_t p = max(pidx[i * N + j], 0);
-              wd = j == i ? TN(0) : fd[p * DZ + z];
-              w2 = j == i ? TN(0) : f2[p * DZ + z];
+              o.wd = j == i ? TN(0) : fd[p * DZ + z];
+              o.w2 = j == i ? TN(0) : f2[p * DZ + z];
             }
-            const TN hj = hvs[j * DZ + z];
-            const TN inv = gi[4 * j + 3];
+            o.hj = hvs[j * DZ + z];
+            o.g0 = gi[4 * j];
+            o.g1 = gi[4 * j + 1];
+            o.g2 = gi[4 * j + 2];
+            o.inv = gi[4 * j + 3];
             const TN* hjc = HT + j * C * LDZ + z;
-            const TN u0 = -gi[4 * j], u1 = -gi[4 * j + 1], u2 = -gi[4 * j + 2];  // (r_i - r_j)_alpha
-            const TN r0 = u0 * inv, r1 = u1 * inv, r2 = u2 * inv;
-            const TN d0 = m0 * wd * u0, d1 = m1 * wd * u1, d2 = m2 * wd * u2;
-            sv0 += d0 * hj;
-            sv1 += d1 * hj;
-            sv2 += d2 * hj;
-            lap += (m0 * (w2 * r0 * r0 + wd * (TN(1) - r0 * r0)) + m1 * (w2 * r1 * r1 + wd * (TN(1) - r1 * r1)) +
-                    m2 * (w2 * r2 * r2 + wd * (TN(1) - r2 * r2))) * hj;
-            if (n > 0) lap += TN(2) * (d0 * hjc[k0 * LDZ] + d1 * hjc[k1 * LDZ] + d2 * hjc[k2 * LDZ]);
+            o.h0 = n > 0 ? hjc[k0 * LDZ] : TN(0);
+            o.h1 = n > 0 ? hjc[k1 * LDZ] : TN(0);
+            o.h2 = n > 0 ? hjc[k2 * LDZ] : TN(0);
+            return o;
+          };
+          auto use_own = [&](const Own& o) {
+            const TN u0 = -o.g0, u1 = -o.g1, u2 = -o.g2;  // (r_i - r_j)_alpha
+            const TN r0 = u0 * o.inv, r1 = u1 * o.inv, r2 = u2 * o.inv;
+            const TN d0 = m0 * o.wd * u0, d1 = m1 * o.wd * u1, d2 = m2 * o.wd * u2;
+            sv0 += d0 * o.hj;
+            sv1 += d1 * o.hj;
+            sv2 += d2 * o.hj;
+            lap += (m0 * (o.w2 * r0 * r0 + o.wd * (TN(1) - r0 * r0)) + m1 * (o.w2 * r1 * r1 + o.wd * (TN(1) - r1 * r1)) +
+                    m2 * (o.w2 * r2 * r2 + o.wd * (TN(1) - r2 * r2))) * o.hj;
+            lap += TN(2) * (d0 * o.h0 + d1 * o.h1 + d2 * o.h2);  // h tangents are zero at n = 0
+          };
+          int j = j_lo;
+          for (; sizeof(TN) == 4 && j + 1 < j_hi; j += 2) {
+            const Own oa = load_own(j), ob = load_own(j + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            use_own(oa);
+            use_own(ob);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          for (; j < j_hi; ++j) {
+            const Own oa = load_own(j);
+            __builtin_amdgcn_sched_barrier(0);
+            use_own(oa);
+            __builtin_amdgcn_sched_barrier(0);
           }
 #pragma unroll
           for (int c = 0; c < C; ++c) {
@@ -252,7 +351,8 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
         }
 #pragma unroll
         for (int c = 0; c < LC; ++c) zi[c * LDZ] = acc[c];
-        // sources from the coordinates of the chunk's other electrons k
+        // sources from the coordinates of the chunk's other electrons k (read,
+        // update, write the item's own Z entries; masked columns are left alone)
         for (int k = max(e_lo, j_lo); k <= min(e_hi, j_hi - 1); ++k) {
           if (k == i) continue;
           const TN* gk = cg + ((size_t)(k - e_lo) * N + i) * 4;  // r_i - r_k
@@ -267,61 +367,36 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
           }
           const TN hk = hvs[k * DZ + z];
           const TN* hkc = HT + (size_t)k * C * LDZ + z;
+          const int cb = 3 * k - a0;
+          int cc[3];
+          TN ua[3], hc[3], zv[3];
+          bool ok[3];
 #pragma unroll
           for (int al = 0; al < 3; ++al) {
-            const int c = 3 * k + al - a0;
-            if (c < 0 || c >= Tc) continue;
-            const TN ua = gk[al];
-            const TN ur = ua * gk[3];
-            const TN dw = -wd * ua;  // d/dr_k of w(|r_i - r_k|)
-            zi[c * LDZ] += dw * hk;
-            lap += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * hk;
-            if (n > 0) lap += TN(2) * dw * hkc[c * LDZ];
+            ok[al] = cb + al >= 0 && cb + al < Tc;
+            cc[al] = min(max(cb + al, 0), LC);
+            ua[al] = gk[al];
+            hc[al] = n > 0 ? hkc[cc[al] * LDZ] : TN(0);
+            zv[al] = zi[cc[al] * LDZ];
+          }
+          const TN inv = gk[3];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int al = 0; al < 3; ++al) {
+            const TN ur = ua[al] * inv;
+            const TN dw = -wd * ua[al];  // d/dr_k of w(|r_i - r_k|)
+            const TN m = ok[al] ? TN(1) : TN(0);
+            lap += m * ((w2 * ur * ur + wd * (TN(1) - ur * ur)) * hk + TN(2) * dw * hc[al]);
+            if (ok[al]) zi[cc[al] * LDZ] = zv[al] + dw * hk;
           }
         }
         zi[LC * LDZ] = lap;
       }
       __syncthreads();
-      gemm_mfma<TN>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
+      gemm_mfma<TN, true>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
+      if (ch == 0) gemm_mfma_window<TN>(ZN, LDZ, R, e_lo * C, NCE * C, DZ, P + Lp.gW[2], DX, XT, LDX, bf16);
       __syncthreads();
     }
-    // nuclear channel: only rows of the chunk's own electrons are non-zero
-    for (int q = threadIdx.x; q < NCE * DZ; q += blockDim.x) {
-      const int i = e_lo + q / DZ, z = q % DZ;
-      TN* zi = ZT + (size_t)i * C * LDZ + z;
-      TN acc[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = 0;
-      const int c0 = 3 * i - a0;
-      for (int I = 0; I < d.NN; ++I) {
-        const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
-        const TN y = P[pl.Y + I * DZ + z];
-        TN wd, w2;
-        if constexpr (STAGE) {
-          wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
-          w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
-        } else {
-          const int64_t p = d.n_ee + i * d.NN + I;
-          wd = fd[p * DZ + z];
-          w2 = f2[p * DZ + z];
-        }
-#pragma unroll
-        for (int c = 0; c < T; ++c) {
-          const int al = c - c0;
-          if (al < 0 || al > 2 || c >= Tc) continue;
-          const TN ua = gn[al];
-          const TN ur = ua * gn[3];
-          acc[c] += wd * ua * y;
-          acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) zi[c * LDZ] = acc[c];
-    }
-    __syncthreads();
-    gemm_mfma<TN>(ZT + (size_t)e_lo * C * LDZ, LDZ, NCE * C, DZ, P + Lp.gW[2], DX, XT + (size_t)e_lo * C * LDX, LDX,
-                  true, bf16);
-    __syncthreads();
   }
   if (xsave) {
     TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (d.L - 1)) * R * DX;
@@ -330,7 +405,6 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
   // The heads' activation slopes (kappa [2][2][N][DX], then eta [2][2][DX])
   // go to the staging region, which the layers no longer need; the copy is
   // issued before the Jastrow sum so its latency overlaps that work.
-  const int nce_max = min(N, T / 3 + 2);
   const bool hstage = STAGE && d.n_ee * DZ + 2 * nce_max * NP * DZ >= 4 * N * DX + 4 * DX;
   if (hstage) {
     copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V);
@@ -353,7 +427,7 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
     for (int lay = 0; lay < 2; ++lay) {
       TN* Sin = lay == 0 ? S0 : S1;
       TN* Sout = lay == 0 ? S1 : S0;
-      gemm_mfma<TN>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
+      gemm_mfma<TN, true>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
       __syncthreads();
       const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
       for (int x = threadIdx.x; x < DX; x += blockDim.x) {
@@ -385,7 +459,7 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
   if (d.flags & PN_NET_NO_BACKFLOW) {
     for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
   } else {
-    gemm_mfma<TN>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
+    gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
     __syncthreads();
     for (int lay = 0; lay < 2; ++lay) {
       TN* A = lay == 0 ? KT : XT;
@@ -405,7 +479,7 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
       }
       __syncthreads();
       if (lay == 0) {
-        gemm_mfma<TN>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+        gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
         __syncthreads();
       }
     }

@@ -103,9 +103,18 @@ struct MfmaChain<float, KQ> {
   }
 };
 
-template <typename TN, int KQ, bool WT = false>
+// WIN: a row window.  Only output rows [lo, lo + n) receive a product, and
+// their A rows are X[row - lo]; tiles that miss the window are skipped.  The
+// tile-to-wave assignment depends only on rows and O, so a windowed product
+// and a full one over the same output share it: each output element is
+// updated by the same wave in both, and the two need no barrier between them.
+// PAIR (FP32 and BF16 forms): whole row tiles are taken two at a time and
+// without per-element bounds tests (more registers, half the exposed LDS
+// latency).
+template <typename TN, int KQ, bool WT = false, bool WIN = false, bool PAIR = false>
 __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int ldw, int O,
-                                            int ncol, TN* Y, int ldy, bool accumulate, bool bf16) {
+                                            int ncol, TN* Y, int ldy, bool accumulate, bool bf16, int lo = 0,
+                                            int n = 0) {
   typedef typename MfmaTile<TN>::acc_t acc_t;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
@@ -122,35 +131,88 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
     rt0 = wv / n_ct;
     rt_step = nwv / n_ct;
   }
+  constexpr bool kPair = PAIR && !WIN && sizeof(TN) == 4;
+  // A fragment of row tile rt: 16-byte reads, so each group of 8 lanes
+  // covers every LDS bank once (rows are padded by 16 bytes); element-wise
+  // reads of the same rows hit each bank up to four times.  Rows and
+  // lane-group offsets are 16-byte aligned for every caller (row strides
+  // from ld_pad, KQ * size a multiple of 16 bytes).
+  auto load_a = [&](int rt, TN* afrag) {
+    const int rw = (rt << 4) + c16 - lo;
+    const bool inw = !WIN || (rw >= 0 && rw < n);
+    const int r = WIN ? (inw ? rw : 0) : min((rt << 4) + c16, rows - 1);
+    const TN* xr = X + (size_t)r * ldx + g * KQ;
+    if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
+      constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
+      const uint4* xv = reinterpret_cast<const uint4*>(xr);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const uint4 q = xv[k];
+        __builtin_memcpy(&afrag[k * PV], &q, 16);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) afrag[s] = xr[s];
+    }
+    if constexpr (WIN) {
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) afrag[s] = inw ? afrag[s] : TN(0);
+    }
+  };
   for (int ct = ct0; ct < n_ct; ct += ct_step) {
     const int col = (ct << 4) + c16;
     const bool colok = col < ncol;
+    const bool colfull = (ct << 4) + 16 <= ncol;  // wave-uniform
     TN bfrag[KQ];
 #pragma unroll
     for (int s = 0; s < KQ; ++s)
       bfrag[s] = colok ? (WT ? W[(size_t)col * ldw + g * KQ + s] : W[(size_t)(g * KQ + s) * ldw + col]) : TN(0);
-    for (int rt = rt0; rt < n_rt; rt += rt_step) {
-      const int r = min((rt << 4) + c16, rows - 1);
-      const TN* xr = X + (size_t)r * ldx + g * KQ;
-      TN afrag[KQ];
-      // 16-byte reads: each group of 8 lanes then covers every LDS bank once
-      // (rows are padded by 16 bytes); element-wise reads of the same rows
-      // hit each bank up to four times.  Rows and lane-group offsets are
-      // 16-byte aligned for every caller (row strides from ld_pad, KQ * size
-      // a multiple of 16 bytes).
-      if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
-        constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
-        const uint4* xv = reinterpret_cast<const uint4*>(xr);
+    int rt = rt0;
+    // Pairs of whole tiles: both tiles' operand and output reads are issued
+    // before the two (independent) MFMA chains, and no element needs a
+    // bounds test.
+    if constexpr (kPair) {
+      for (; colfull && rt + rt_step < n_rt && ((rt + rt_step) << 4) + 16 <= rows; rt += 2 * rt_step) {
+        const int rtb = rt + rt_step;
+        TN afa[KQ], afb[KQ];
+        load_a(rt, afa);
+        load_a(rtb, afb);
+        acc_t ca, cb;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-          const uint4 q = xv[k];
-          __builtin_memcpy(&afrag[k * PV], &q, 16);
+        for (int v = 0; v < 4; ++v) {
+          const int row = MfmaTile<TN>::row_of(lane, v);
+          ca[v] = accumulate ? Y[(size_t)((rt << 4) + row) * ldy + col] : TN(0);
+          cb[v] = accumulate ? Y[(size_t)((rtb << 4) + row) * ldy + col] : TN(0);
         }
-      } else {
+        ca = MfmaChain<TN, KQ>::run(afa, bfrag, ca, bf16);
+        cb = MfmaChain<TN, KQ>::run(afb, bfrag, cb, bf16);
 #pragma unroll
-        for (int s = 0; s < KQ; ++s) afrag[s] = xr[s];
+        for (int v = 0; v < 4; ++v) {
+          const int row = MfmaTile<TN>::row_of(lane, v);
+          Y[(size_t)((rt << 4) + row) * ldy + col] = ca[v];
+          Y[(size_t)((rtb << 4) + row) * ldy + col] = cb[v];
+        }
       }
+    }
+    for (; rt < n_rt; rt += rt_step) {
+      if (WIN && ((rt << 4) >= lo + n || (rt << 4) + 16 <= lo)) continue;  // wave-uniform
+      TN afrag[KQ];
+      load_a(rt, afrag);
       acc_t c;
+      if (kPair && colfull && (rt << 4) + 16 <= rows) {  // whole tile: no per-element tests
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
+          c[v] = accumulate ? Y[(size_t)row * ldy + col] : TN(0);
+        }
+        c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
+          Y[(size_t)row * ldy + col] = c[v];
+        }
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -189,16 +251,32 @@ __device__ __forceinline__ void gemm_mfma_cols(const TN* X, int ldx, int rows, i
   }
 }
 
-template <typename TN>
+template <typename TN, bool PAIR = false>
 __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W, int O,
                                           TN* Y, int ldy, bool accumulate, bool bf16) {
   switch (I) {
-    case 16: gemm_mfma_k<TN, 4>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    case 32: gemm_mfma_k<TN, 8>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    case 64: gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    case 16: gemm_mfma_k<TN, 4, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    case 32: gemm_mfma_k<TN, 8, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
+    case 64: gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
     default:
-      gemm_mfma_k<TN, 16>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
-      gemm_mfma_k<TN, 16>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
+      gemm_mfma_k<TN, 16, false, false, PAIR>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      break;
+  }
+}
+
+// Y[lo + r][O] += X[r][I] * W for r < n, as the windowed form above: it may
+// follow a gemm_mfma over the same Y, rows and O without a barrier.
+template <typename TN>
+__device__ __forceinline__ void gemm_mfma_window(const TN* X, int ldx, int rows, int lo, int n, int I,
+                                                 const TN* __restrict__ W, int O, TN* Y, int ldy, bool bf16) {
+  switch (I) {
+    case 16: gemm_mfma_k<TN, 4, false, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n); break;
+    case 32: gemm_mfma_k<TN, 8, false, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n); break;
+    case 64: gemm_mfma_k<TN, 16, false, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n); break;
+    default:
+      gemm_mfma_k<TN, 16, false, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n);
+      gemm_mfma_k<TN, 16, false, true>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16, lo, n);
       break;
   }
 }
