@@ -47,23 +47,15 @@ constexpr int kThreadsT = 256;
 
 namespace {
 
-// Block-wide copy of n 16-byte units: every thread issues the four loads of
-// a round before its stores, so a copy costs about one memory latency per
-// round of 4 * blockDim units rather than one per element.
-__device__ __forceinline__ void copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int n) {
-  const int nt = (int)blockDim.x, t0 = (int)threadIdx.x;
-  const uint4 z = {0u, 0u, 0u, 0u};
-  for (int base = 0; base < n; base += 4 * nt) {
-    const int q0 = base + t0, q1 = q0 + nt, q2 = q1 + nt, q3 = q2 + nt;
-    const uint4 v0 = q0 < n ? src[q0] : z;
-    const uint4 v1 = q1 < n ? src[q1] : z;
-    const uint4 v2 = q2 < n ? src[q2] : z;
-    const uint4 v3 = q3 < n ? src[q3] : z;
-    if (q0 < n) dst[q0] = v0;
-    if (q1 < n) dst[q1] = v1;
-    if (q2 < n) dst[q2] = v2;
-    if (q3 < n) dst[q3] = v3;
-  }
+// Block-wide global-to-LDS copy of n 16-byte units without registers: wave
+// wv moves runs of 64 units, lane l the l-th unit of a run (the LDS address
+// of a run is wave-uniform, as the load-to-LDS instruction requires).  The
+// data land asynchronously; a barrier (which waits for outstanding loads)
+// makes them visible.
+__device__ __forceinline__ void dma16(uint4* __restrict__ dst, const uint4* __restrict__ src, int n, int lane,
+                                      int wv, int nwv) {
+  for (int b = wv * 64; b < n; b += nwv * 64)
+    if (b + lane < n) __builtin_amdgcn_global_load_lds(src + b + lane, dst + b, 16, 0, 0);
 }
 
 // BF16 is a template parameter so that the FP32 and FP64 instantiations
@@ -150,44 +142,44 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
     const TN* fd = fw + (int64_t)d.n_pairs * DZ;       // w'/d
     const TN* f2 = fw + (int64_t)2 * d.n_pairs * DZ;   // w''
     const TN* hv = hval + (w * d.L + n) * N * DZ;
-    copy16(reinterpret_cast<uint4*>(hvs), reinterpret_cast<const uint4*>(hv), N * DZ / V);
     // the adjoint pass re-reads the layer inputs x^(n), n >= 1 (x^(0) has no tangents)
     if (xsave && n > 0) {
       TN* xs = xsave + (((size_t)w * n_chunks + chunk) * d.L + (n - 1)) * R * DX;
       for (int q = threadIdx.x; q < R * DX; q += blockDim.x) xs[q] = XT[(q / DX) * LDX + q % DX];
     }
-    if constexpr (STAGE) {
-      copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(fv), d.n_ee * DZ / V);
-      // rows (chunk electron k, partner) of w'/d and w'': 16-byte units, two
-      // rounds of loads in flight per thread
-      const int U16 = DZ / V, n16 = NCE * NP * U16;
-      const uint4 z4 = {0u, 0u, 0u, 0u};
-      for (int base = 0; base < n16; base += 2 * (int)blockDim.x) {
-        const int q0 = base + (int)threadIdx.x, q1 = q0 + (int)blockDim.x;
-        int64_t p0 = -1, p1 = -1;
-        if (q0 < n16) {
-          const int row = q0 / U16, k = e_lo + row / NP, part = row % NP;
-          p0 = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
-        }
-        if (q1 < n16) {
-          const int row = q1 / U16, k = e_lo + row / NP, part = row % NP;
-          p1 = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
-        }
-        const uint4 a0 = p0 >= 0 ? reinterpret_cast<const uint4*>(fd + p0 * DZ)[q0 % U16] : z4;
-        const uint4 b0 = p0 >= 0 ? reinterpret_cast<const uint4*>(f2 + p0 * DZ)[q0 % U16] : z4;
-        const uint4 a1 = p1 >= 0 ? reinterpret_cast<const uint4*>(fd + p1 * DZ)[q1 % U16] : z4;
-        const uint4 b1 = p1 >= 0 ? reinterpret_cast<const uint4*>(f2 + p1 * DZ)[q1 % U16] : z4;
-        if (q0 < n16) {
-          reinterpret_cast<uint4*>(wds)[q0] = a0;
-          reinterpret_cast<uint4*>(w2s)[q0] = b0;
-        }
-        if (q1 < n16) {
-          reinterpret_cast<uint4*>(wds)[q1] = a1;
-          reinterpret_cast<uint4*>(w2s)[q1] = b1;
+    // Staging of the layer's tables: h values, then (STAGE) the filter values
+    // of all electron pairs and the rows (chunk electron k, partner) of w'/d
+    // and w''.  Global-to-LDS loads (16 bytes per lane, no registers): all of
+    // them are in flight together, and the h product below proceeds while
+    // they land; the barrier after it waits for them.
+    {
+      const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6, nwv = (int)blockDim.x >> 6;
+      dma16(reinterpret_cast<uint4*>(hvs), reinterpret_cast<const uint4*>(hv), N * DZ / V, lane, wv, nwv);
+      if constexpr (STAGE) {
+        dma16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(fv), d.n_ee * DZ / V, lane, wv, nwv);
+        const int U16 = DZ / V, nD = NCE * NP * U16;
+        const uint4 z4 = {0u, 0u, 0u, 0u};
+        for (int b = wv * 64; b < nD; b += nwv * 64) {
+          const int q = b + lane;
+          int64_t p = -1;
+          if (q < nD) {
+            const int row = q / U16, k = e_lo + row / NP, part = row % NP;
+            p = part < N ? (part == k ? -1 : pidx[k * N + part]) : d.n_ee + k * d.NN + (part - N);
+          }
+          if (p >= 0) {
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(fd + p * DZ) + q % U16,
+                                             reinterpret_cast<uint4*>(wds) + b, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(f2 + p * DZ) + q % U16,
+                                             reinterpret_cast<uint4*>(w2s) + b, 16, 0, 0);
+          } else if (q < nD) {  // a chunk electron paired with itself: zeros
+            reinterpret_cast<uint4*>(wds)[q] = z4;
+            reinterpret_cast<uint4*>(w2s)[q] = z4;
+          }
         }
       }
+      if (n > 0) gemm_mfma<TN, true>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
     }
-    if (n > 0) gemm_mfma<TN, true>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads to LDS have landed
     __syncthreads();
     for (int ch = 0; ch < 2; ++ch) {
       // channel 0 also takes the nuclear messages, which only rows of the
@@ -407,89 +399,110 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
   // issued before the Jastrow sum so its latency overlaps that work.
   const bool hstage = STAGE && d.n_ee * DZ + 2 * nce_max * NP * DZ >= 4 * N * DX + 4 * DX;
   if (hstage) {
-    copy16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V);
-    copy16(reinterpret_cast<uint4*>(wvs + 4 * N * DX), reinterpret_cast<const uint4*>(ecoef + w * 4 * DX), 4 * DX / V);
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6, nwv = (int)blockDim.x >> 6;
+    dma16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V, lane,
+          wv, nwv);
+    dma16(reinterpret_cast<uint4*>(wvs + 4 * N * DX), reinterpret_cast<const uint4*>(ecoef + w * 4 * DX), 4 * DX / V,
+          lane, wv, nwv);
   }
-  // ---- Jastrow head on sum_i x_i, rows = columns (J = 0 without it) ----
+  // ---- heads: Jastrow on sum_i x_i (rows = columns), backflow per row ----
+  // The two heads are independent chains of products and activations; they
+  // advance together, one step of each between barriers.  Without the
+  // Jastrow factor J = 0, without the backflow f = 1 (no tangents).
+  const bool do_j = !(d.flags & PN_NET_NO_JASTROW), do_k = !(d.flags & PN_NET_NO_BACKFLOW);
   double* jt = jtan + ((int64_t)w * n_chunks + chunk) * C;
-  if (d.flags & PN_NET_NO_JASTROW) {
-    for (int col = threadIdx.x; col < C; col += blockDim.x) jt[col] = 0.0;
-  } else {
-    TN* S0 = ES;             // [C][LDX]
-    TN* S1 = ES + C * LDX;   // [C][LDX]
+  double* ft = ftan + ((int64_t)w * n_chunks + chunk) * N * C * M;
+  TN* S0 = ES;             // [C][LDX]
+  TN* S1 = ES + C * LDX;   // [C][LDX]
+  // Jastrow activation in place: s1 v per column, s1 v_L + s2 sum_a v_a^2
+  auto act_j = [&](TN* S, int lay) {
+    const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
+    for (int x = threadIdx.x; x < DX; x += blockDim.x) {
+      const TN s1 = ec[x], s2 = ec[DX + x];
+      TN v[LC];
+#pragma unroll
+      for (int col = 0; col < LC; ++col) v[col] = S[col * LDX + x];
+      const TN vl = S[LC * LDX + x];
+      TN sq = 0;
+#pragma unroll
+      for (int col = 0; col < LC; ++col) {
+        sq += v[col] * v[col];
+        S[col * LDX + x] = s1 * v[col];
+      }
+      S[LC * LDX + x] = s1 * vl + s2 * sq;
+    }
+  };
+  // backflow activation in place, rows (i, column)
+  auto act_k = [&](TN* A, int lay) {
+    const TN* kc = hstage ? wvs + lay * 2 * N * DX : kcoef + (w * 2 + lay) * 2 * N * DX;
+    for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
+      const int i = q / DX, x = q % DX;
+      const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
+      TN* ai = A + (size_t)i * C * LDX + x;
+      TN v[LC];
+#pragma unroll
+      for (int col = 0; col < LC; ++col) v[col] = ai[col * LDX];
+      const TN vl = ai[LC * LDX];
+      TN sq = 0;
+#pragma unroll
+      for (int col = 0; col < LC; ++col) {
+        sq += v[col] * v[col];
+        ai[col * LDX] = s1 * v[col];
+      }
+      ai[LC * LDX] = s1 * vl + s2 * sq;
+    }
+  };
+  if (do_j) {
     for (int q = threadIdx.x; q < C * DX; q += blockDim.x) {
       const int col = q / DX, x = q % DX;
+      const TN* xc = XT + (size_t)col * LDX + x;
       TN s = 0;
-      for (int i = 0; i < N; ++i) s += XT[((size_t)i * C + col) * LDX + x];
+      int i = 0;
+      for (; i + 3 < N; i += 4) {  // four reads in flight
+        const TN a = xc[(size_t)i * C * LDX], b = xc[(size_t)(i + 1) * C * LDX];
+        const TN e = xc[(size_t)(i + 2) * C * LDX], f = xc[(size_t)(i + 3) * C * LDX];
+        __builtin_amdgcn_sched_barrier(0);
+        s += a + b + e + f;
+      }
+      for (; i < N; ++i) s += xc[(size_t)i * C * LDX];
       S0[col * LDX + x] = s;
     }
-    __syncthreads();
-    for (int lay = 0; lay < 2; ++lay) {
-      TN* Sin = lay == 0 ? S0 : S1;
-      TN* Sout = lay == 0 ? S1 : S0;
-      gemm_mfma<TN, true>(Sin, LDX, C, DX, P + (lay == 0 ? pl.eW1 : pl.eW2), DX, Sout, LDX, false, bf16);
-      __syncthreads();
-      const TN* ec = hstage ? wvs + 4 * N * DX + lay * 2 * DX : ecoef + (w * 2 + lay) * 2 * DX;
-      for (int x = threadIdx.x; x < DX; x += blockDim.x) {
-        const TN s1 = ec[x], s2 = ec[DX + x];
-        TN sq = 0;
-#pragma unroll
-        for (int col = 0; col < LC; ++col) {
-          const TN v = Sout[col * LDX + x];
-          sq += v * v;
-          Sout[col * LDX + x] = s1 * v;
-        }
-        Sout[LC * LDX + x] = s1 * Sout[LC * LDX + x] + s2 * sq;
-      }
-      __syncthreads();
-    }
-    {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
-        TN acc = 0;
-        for (int x = lane; x < DX; x += 64)
-          acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0) jt[col] = (double)acc;
-      }
+  } else {
+    for (int col = threadIdx.x; col < C; col += blockDim.x) jt[col] = 0.0;
+  }
+  if (do_k)
+    gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
+  else
+    for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
+  __builtin_amdgcn_s_waitcnt(0);  // the staged activation slopes have landed
+  __syncthreads();
+  if (do_j) gemm_mfma<TN, true>(S0, LDX, C, DX, P + pl.eW1, DX, S1, LDX, false, bf16);
+  if (do_k) act_k(KT, 0);
+  __syncthreads();
+  if (do_j) act_j(S1, 0);
+  if (do_k) gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+  __syncthreads();
+  if (do_j) gemm_mfma<TN, true>(S1, LDX, C, DX, P + pl.eW2, DX, S0, LDX, false, bf16);
+  if (do_k) act_k(XT, 1);
+  __syncthreads();
+  if (do_j) act_j(S0, 1);
+  if (do_k) gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+  __syncthreads();
+  if (do_j) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {
+      TN acc = 0;
+      for (int x = lane; x < DX; x += 64)
+        acc += maybe_bf16(S0[col * LDX + x], bf16) * maybe_bf16(P[pl.eW3 + x], bf16);
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) jt[col] = (double)acc;
     }
   }
-  // ---- backflow head (f = 1, no tangents, without it) ----
-  double* ft = ftan + ((int64_t)w * n_chunks + chunk) * N * C * M;
-  if (d.flags & PN_NET_NO_BACKFLOW) {
-    for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
-  } else {
-    gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
-    __syncthreads();
-    for (int lay = 0; lay < 2; ++lay) {
-      TN* A = lay == 0 ? KT : XT;
-      const TN* kc = hstage ? wvs + lay * 2 * N * DX : kcoef + (w * 2 + lay) * 2 * N * DX;
-      for (int q = threadIdx.x; q < N * DX; q += blockDim.x) {
-        const int i = q / DX, x = q % DX;
-        const TN s1 = kc[i * DX + x], s2 = kc[N * DX + i * DX + x];
-        TN sq = 0;
-        TN* ai = A + (size_t)i * C * LDX + x;
-#pragma unroll
-        for (int col = 0; col < LC; ++col) {
-          const TN v = ai[col * LDX];
-          sq += v * v;
-          ai[col * LDX] = s1 * v;
-        }
-        ai[LC * LDX] = s1 * ai[LC * LDX] + s2 * sq;
-      }
-      __syncthreads();
-      if (lay == 0) {
-        gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
-        __syncthreads();
-      }
-    }
-    gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
-    __syncthreads();
+  if (do_k)
     for (int q = threadIdx.x; q < R * M; q += blockDim.x) {
       const int row = q / M, mu = q % M;
       ft[(int64_t)row * M + mu] = (double)KT[(size_t)row * LDX + mu];
     }
-  }
 }
 
 template <typename TN, int C, bool STAGE>
