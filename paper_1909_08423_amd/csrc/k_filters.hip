@@ -33,10 +33,12 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
   const int rows = (int)min((int64_t)PT, nrows - row0);
   const int K = d.K, DZ = d.DZ;
   const int LDK = ld_pad<TN>(K), LDZ = ld_pad<TN>(DZ);
-  double* dd = reinterpret_cast<double*>(smem);   // [PT]
-  TN* E = reinterpret_cast<TN*>(dd + PT);         // [3][PT][LDK]
-  TN* U = E + 3 * PT * LDK;                       // [3][PT][LDZ]
-  TN* O = U + 3 * PT * LDZ;                       // [3][PT][LDZ]
+  double* dd = reinterpret_cast<double*>(smem);       // [PT] distances
+  int64_t* doff = reinterpret_cast<int64_t*>(dd + PT);  // [PT] output offset of each row
+  TN* E = reinterpret_cast<TN*>(doff + PT);           // [3][PT][max(LDK, LDZ)]
+  TN* U = E + 3 * PT * max(LDK, LDZ);                 // [3][PT][LDZ]
+  TN* O = E;                                          // [3][PT][LDZ], over E once E is consumed
+  const int64_t lstride = (int64_t)3 * d.n_pairs * DZ;
 
   // --- distances ---
   for (int q = threadIdx.x; q < rows; q += blockDim.x) {
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
       z = rw[3 * i + 2] - t.nuc_xyz[3 * I + 2];
     }
     dd[q] = sqrt(x * x + y * y + z * z);
+    doff[q] = w * (int64_t)d.L * lstride + layer * lstride + (int64_t)p * DZ;
   }
   __syncthreads();
   // --- feature jets (computed in FP64, stored in the network type) ---
@@ -97,16 +100,18 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
   // --- second Linear, again over the stacked jets ---
   gemm_mfma<TN>(U, LDZ, 3 * PT, DZ, P + Lp.w2W[ch], DZ, O, LDZ, false, bf16);
   __syncthreads();
-  // --- store as [walker][layer][jet][pair][DZ]; bias on the value ---
-  const int64_t lstride = (int64_t)3 * d.n_pairs * DZ;
-  for (int q = threadIdx.x; q < 3 * rows * DZ; q += blockDim.x) {
-    int jet = q / (rows * DZ), rem = q % (rows * DZ), row = rem / DZ, o = rem % DZ;
-    TN v = O[(jet * PT + row) * LDZ + o];
-    if (jet == 0) v += P[Lp.w2b[ch] + o];
-    int64_t g = row0 + row;
-    int64_t w = g / np;
-    int p = p_lo + (int)(g % np);
-    filt[w * (int64_t)d.L * lstride + layer * lstride + ((int64_t)jet * d.n_pairs + p) * DZ + o] = v;
+  // --- store as [walker][layer][jet][pair][DZ] in 16-byte units; bias on
+  // the value ---
+  constexpr int V = 16 / sizeof(TN);
+  const int DV = DZ / V;
+  for (int q = threadIdx.x; q < 3 * rows * DV; q += blockDim.x) {
+    const int jet = q / (rows * DV), rem = q % (rows * DV), row = rem / DV, o = (rem % DV) * V;
+    TN v[V];
+    __builtin_memcpy(v, O + (jet * PT + row) * LDZ + o, 16);
+    if (jet == 0)
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[e] += P[Lp.w2b[ch] + o + e];
+    __builtin_memcpy(filt + doff[row] + (int64_t)jet * d.n_pairs * DZ + o, v, 16);
   }
 }
 
@@ -114,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void k_filters(Dims d, DevTables t, int64
 
 template <typename TN>
 size_t filter_lds_bytes(const Dims& d, int PT) {
-  return PT * sizeof(double) + (size_t)3 * PT * (ld_pad<TN>(d.K) + 2 * ld_pad<TN>(d.DZ)) * sizeof(TN);
+  return PT * (sizeof(double) + sizeof(int64_t)) +
+         (size_t)3 * PT * (std::max(ld_pad<TN>(d.K), ld_pad<TN>(d.DZ)) + ld_pad<TN>(d.DZ)) * sizeof(TN);
 }
 template size_t filter_lds_bytes<double>(const Dims&, int);
 template size_t filter_lds_bytes<float>(const Dims&, int);

@@ -57,22 +57,40 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
     __syncthreads();
     for (int ch = 0; ch < 3; ++ch) {
       for (int q = threadIdx.x; q < R * DZ; q += blockDim.x) {
-        int row = q / DZ, z = q % DZ, wl = row / N, i = row % N;
+        const int row = q / DZ, z = q % DZ, wl = row / N, i = row % N;
         const TN* fw = filt + (w0 + wl) * fw_stride + n * fl_stride;  // jet 0 = value
         TN acc = 0;
         if (ch < 2) {
-          bool up_i = i < d.n_up;
-          for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            bool same = (j < d.n_up) == up_i;
-            if (same != (ch == 0)) continue;
-            int p = pidx[i * N + j];
-            acc += fw[(int64_t)p * DZ + z] * H[(wl * N + j) * LDW + z];
+          // electrons of this channel: same spin (ch 0) or opposite spin
+          // (ch 1); j = i contributes w = 0.  Four partners per step, their
+          // global and LDS reads issued before the products.
+          const bool want_up = (ch == 0) == (i < d.n_up);
+          const int j_lo = want_up ? 0 : d.n_up, j_hi = want_up ? d.n_up : N;
+          const TN* hw = H + (size_t)wl * N * LDW + z;
+          for (int j = j_lo; j < j_hi; j += 4) {
+            TN wv[4], hv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int jj = min(j + k, j_hi - 1);
+              wv[k] = fw[(int64_t)max(pidx[i * N + jj], 0) * DZ + z];
+              hv[k] = hw[(size_t)jj * LDW];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += (j + k < j_hi && j + k != i) ? wv[k] * hv[k] : TN(0);
           }
         } else {
-          for (int I = 0; I < d.NN; ++I) {
-            int p = d.n_ee + i * d.NN + I;
-            acc += fw[(int64_t)p * DZ + z] * P[pl.Y + I * DZ + z];
+          for (int I = 0; I < d.NN; I += 4) {
+            TN wv[4], yv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int II = min(I + k, d.NN - 1);
+              wv[k] = fw[(int64_t)(d.n_ee + i * d.NN + II) * DZ + z];
+              yv[k] = P[pl.Y + II * DZ + z];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += I + k < d.NN ? wv[k] * yv[k] : TN(0);
           }
         }
         Z[row * LDW + z] = acc;
@@ -80,9 +98,13 @@ __global__ __launch_bounds__(kThreads) void k_net_value(Dims d, DevTables t, int
       __syncthreads();
       gemm_mfma<TN>(Z, LDW, R, DZ, P + Lp.gW[ch], DX, X, LDX, true, bf16);
       __syncthreads();
-      for (int q = threadIdx.x; q < R * DX; q += blockDim.x) X[(q / DX) * LDX + q % DX] += P[Lp.gb[ch] + q % DX];
-      __syncthreads();
     }
+    // the three channels' biases, added once
+    for (int q = threadIdx.x; q < R * DX; q += blockDim.x) {
+      const int x = q % DX;
+      X[(q / DX) * LDX + x] += P[Lp.gb[0] + x] + P[Lp.gb[1] + x] + P[Lp.gb[2] + x];
+    }
+    __syncthreads();
   }
   if (xval)
     for (int q = threadIdx.x; q < R * DX; q += blockDim.x)
