@@ -385,8 +385,15 @@ __global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables 
         zi[LC * LDZ] = lap;
       }
       __syncthreads();
-      gemm_mfma<TN, true>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
-      if (ch == 0) gemm_mfma_window<TN>(ZN, LDZ, R, e_lo * C, NCE * C, DZ, P + Lp.gW[2], DX, XT, LDX, bf16);
+      // channel 0 with the nuclear rows in one pass over the tiles, both weight
+      // slabs read up front (FP32 only: FP64 and BF16 spill with it)
+      if (sizeof(TN) == 4 && !BF16 && ch == 0) {
+        gemm_mfma_dual<TN, true>(ZT, LDZ, R, DZ, P + Lp.gW[0], DX, XT, LDX, ZN, LDZ, e_lo * C, NCE * C,
+                                 P + Lp.gW[2], bf16);
+      } else {
+        gemm_mfma<TN, true>(ZT, LDZ, R, DZ, P + Lp.gW[ch], DX, XT, LDX, true, bf16);
+        if (ch == 0) gemm_mfma_window<TN>(ZN, LDZ, R, e_lo * C, NCE * C, DZ, P + Lp.gW[2], DX, XT, LDX, bf16);
+      }
       __syncthreads();
     }
   }

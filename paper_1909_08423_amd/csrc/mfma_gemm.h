@@ -111,10 +111,14 @@ struct MfmaChain<float, KQ> {
 // PAIR (FP32 and BF16 forms): whole row tiles are taken two at a time and
 // without per-element bounds tests (more registers, half the exposed LDS
 // latency).
-template <typename TN, int KQ, bool WT = false, bool WIN = false, bool PAIR = false>
+// DUAL: a second product on a row window, X2[row - lo] * W2 for output rows
+// [lo, lo + n), summed into the same tiles as the full product X * W (its
+// weight slab is read together with the first one).
+template <typename TN, int KQ, bool WT = false, bool WIN = false, bool PAIR = false, bool DUAL = false>
 __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int ldw, int O,
                                             int ncol, TN* Y, int ldy, bool accumulate, bool bf16, int lo = 0,
-                                            int n = 0) {
+                                            int n = 0, const TN* X2 = nullptr, int ldx2 = 0,
+                                            const TN* __restrict__ W2 = nullptr) {
   typedef typename MfmaTile<TN>::acc_t acc_t;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
@@ -159,6 +163,27 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
       for (int s = 0; s < KQ; ++s) afrag[s] = inw ? afrag[s] : TN(0);
     }
   };
+  // the second product's A fragment (window rows, zero elsewhere)
+  auto load_a2 = [&](int rt, TN* af) {
+    const int rw = (rt << 4) + c16 - lo;
+    const bool inw = rw >= 0 && rw < n;
+    const TN* xr = X2 + (size_t)(inw ? rw : 0) * ldx2 + g * KQ;
+    if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
+      constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
+      const uint4* xv = reinterpret_cast<const uint4*>(xr);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const uint4 q = xv[k];
+        __builtin_memcpy(&af[k * PV], &q, 16);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) af[s] = xr[s];
+    }
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) af[s] = inw ? af[s] : TN(0);
+  };
+  auto meets = [&](int rt) { return (rt << 4) < lo + n && (rt << 4) + 16 > lo; };  // wave-uniform
   for (int ct = ct0; ct < n_ct; ct += ct_step) {
     const int col = (ct << 4) + c16;
     const bool colok = col < ncol;
@@ -167,6 +192,21 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 #pragma unroll
     for (int s = 0; s < KQ; ++s)
       bfrag[s] = colok ? (WT ? W[(size_t)col * ldw + g * KQ + s] : W[(size_t)(g * KQ + s) * ldw + col]) : TN(0);
+    TN bfrag2[DUAL ? KQ : 1];
+    if constexpr (DUAL) {
+#pragma unroll
+      for (int s = 0; s < KQ; ++s) bfrag2[s] = colok ? W2[(size_t)(g * KQ + s) * ldw + col] : TN(0);
+    }
+    auto second = [&](int rt, acc_t c) -> acc_t {
+      if constexpr (DUAL) {
+        if (meets(rt)) {
+          TN a2[KQ];
+          load_a2(rt, a2);
+          c = MfmaChain<TN, KQ>::run(a2, bfrag2, c, bf16);
+        }
+      }
+      return c;
+    };
     int rt = rt0;
     // Pairs of whole tiles: both tiles' operand and output reads are issued
     // before the two (independent) MFMA chains, and no element needs a
@@ -186,6 +226,8 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
         }
         ca = MfmaChain<TN, KQ>::run(afa, bfrag, ca, bf16);
         cb = MfmaChain<TN, KQ>::run(afb, bfrag, cb, bf16);
+        ca = second(rt, ca);
+        cb = second(rtb, cb);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = MfmaTile<TN>::row_of(lane, v);
@@ -206,6 +248,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
           c[v] = accumulate ? Y[(size_t)row * ldy + col] : TN(0);
         }
         c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
+        c = second(rt, c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -219,6 +262,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
         c[v] = (accumulate && row < rows && colok) ? Y[(size_t)row * ldy + col] : TN(0);
       }
       c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
+      c = second(rt, c);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -261,6 +305,31 @@ __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I,
     default:
       gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
       gemm_mfma_k<TN, 16, false, false, PAIR>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      break;
+  }
+}
+
+// Y[rows][O] += X * W + (rows lo .. lo + n) X2[row - lo] * W2, the two with
+// the same I (16, 32, 64 or 128) and O: one pass over the output tiles, and
+// both weight slabs read up front.
+template <typename TN, bool PAIR = false>
+__device__ __forceinline__ void gemm_mfma_dual(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W,
+                                               int O, TN* Y, int ldy, const TN* X2, int ldx2, int lo, int n,
+                                               const TN* __restrict__ W2, bool bf16) {
+  switch (I) {
+    case 16:
+      gemm_mfma_k<TN, 4, false, false, PAIR, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n, X2, ldx2, W2);
+      break;
+    case 32:
+      gemm_mfma_k<TN, 8, false, false, PAIR, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n, X2, ldx2, W2);
+      break;
+    case 64:
+      gemm_mfma_k<TN, 16, false, false, PAIR, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n, X2, ldx2, W2);
+      break;
+    default:
+      gemm_mfma_k<TN, 16, false, false, PAIR, true>(X, ldx, rows, W, O, O, O, Y, ldy, true, bf16, lo, n, X2, ldx2, W2);
+      gemm_mfma_k<TN, 16, false, false, PAIR, true>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true,
+                                                    bf16, lo, n, X2 + 64, ldx2, W2 + (size_t)64 * O);
       break;
   }
 }
