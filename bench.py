@@ -69,11 +69,11 @@ def chunk_T(s, net, prec):
         return 3 * 64 * 8 + ((N * N + 3) & ~3) * 4 + e * tn
 
     def pick(budget):
-        for stage in (True, False):
-            for nc in range(1, 3 * N + 1):
-                T = -(-3 * N // nc)
-                if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
-                    continue
+        for nc in range(1, 3 * N + 1):
+            T = -(-3 * N // nc)
+            if T not in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15):
+                continue
+            for stage in (True, False):
                 if lds(T, stage) <= budget or (not stage and T == 1):
                     return T
         return 1

@@ -163,8 +163,10 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
   WsLayout L{};
   L.full = full;
   // chunking of the 3N coordinates for the tangent pass: the largest chunk
-  // whose block fits the LDS budget, preferring the form that stages the
-  // filter tables in LDS.  Two 256-thread blocks per CU (80 KB each) unless
+  // whose block fits the LDS budget; at equal chunk the form that stages the
+  // filter tables in LDS (measured: a larger chunk without staging beats a
+  // smaller staged one, e.g. Ne-like FP32 T 10 vs 8, 2.25 vs 2.59 ms, and
+  // FP64 T 5 vs 3, 4.28 vs 5.39 ms).  Two 256-thread blocks per CU (80 KB each) unless
   // that leaves chunks of fewer than 3 coordinates (large systems, where the
   // per-chunk work of the heads would be repeated 3N times): then one block
   // per CU with all 160 KB, if that at least doubles the chunk.
@@ -174,11 +176,11 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
   };
   auto pick = [&](size_t budget, int& T_out, bool& stage_out) {
     T_out = 0;
-    for (int pass = 0; pass < 2 && T_out == 0; ++pass) {
-      const bool stage = pass == 0;
-      for (int nc = 1; nc <= ncoord; ++nc) {
-        const int T = (ncoord + nc - 1) / nc;
-        if (!tangent_chunk_supported(T)) continue;
+    for (int nc = 1; nc <= ncoord && T_out == 0; ++nc) {
+      const int T = (ncoord + nc - 1) / nc;
+      if (!tangent_chunk_supported(T)) continue;
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool stage = pass == 0;
         if (lds_of(T, stage) <= budget || (!stage && T == 1)) {
           T_out = T;
           stage_out = stage;
