@@ -17,9 +17,13 @@ the two middle values; clip(E) = m + sgn(E - m) w (1 + ln(|E - m| / w)) for
 decay 0.01; proposals r' = r + sigma xi over all electrons, accepted when
 u < exp(2 (ln|psi'| - ln|psi|)).
 
-Parity pins: Philox against the published known-answer vectors; AdamW
-against torch.optim.AdamW; clipping by continuity and fixed points; the
-gradient estimator against finite differences of the surrogate loss (tests).
+Parity pins: Philox against the published known-answer vectors; the
+proposal normals against Box-Muller values evaluated in 40-digit arithmetic
+from the Philox words; the Metropolis step against the exact moments of
+|psi|^2 for a Gaussian (variance 1/(4a)) and for hydrogen (<r> = 3/2), with
+a planted exp(Delta) acceptance shown to fail those checks; AdamW against
+torch.optim.AdamW; clipping by continuity and fixed points; the gradient
+estimator against finite differences of the surrogate loss (tests).
 """
 
 import math

@@ -359,11 +359,16 @@ def _autograd_function():
             fctx.save_for_backward(params, r)
             fctx.pnctx, fctx.prec = pnctx, prec
             fctx.mark_non_differentiable(out["sign"])
+            # outputs the loss does not use arrive as None, so that a loss on
+            # ln|psi| alone runs the value-path adjoint (the estimator's case)
+            fctx.set_materialize_grads(False)
             return out["logabs"], out["sign"], out["grad"], out["lap"], out["eloc"]
 
         @staticmethod
         def backward(fctx, g_logabs, g_sign, g_grad, g_lap, g_eloc):
             params, r = fctx.saved_tensors
+            if g_logabs is None and g_grad is None and g_lap is None and g_eloc is None:
+                return None, None, None, None
             gp = fctx.pnctx.eval_backward(r.detach(), params.detach(), g_logabs, fctx.prec, ct_grad=g_grad,
                                           ct_lap=g_lap, ct_eloc=g_eloc)
             return gp.to(params.dtype), None, None, None

@@ -125,7 +125,7 @@ def test_mixed_precision_error_statement(pn, idx, prec, bound):
 
 
 # ------------------------------------------------------------- backward ----
-@pytest.mark.parametrize("idx", [1, 2, 3])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5])
 def test_backward_fp64_matches_oracle(pn, idx):
     """Value-path adjoint grad += sum_w ct_w d ln|psi_w| / d theta (the
     gradient the Hermitian estimator of Methods eq. "trainig" needs) against
@@ -249,3 +249,27 @@ def test_edge_batches(pn):
         one, _ = _run(pn, w, w.walkers[k:k + 1], pn.PN_PREC_FP64)
         for key in one:
             np.testing.assert_array_equal(one[key][0], full[key][k])
+
+
+@pytest.mark.parametrize("idx", [2, 5])
+def test_autograd_logabs_only_takes_value_adjoint(pn, idx):
+    """A loss on ln|psi| alone (the Hermitian estimator's surrogate, Methods
+    eq. "trainig") through the autograd Function equals the oracle's
+    value-path gradient, and the call sizes its workspace for the value-path
+    adjoint, not for the full adjoint through the coordinate derivatives."""
+    fx = load_fixture(idx)
+    w = make_config(idx, n_walkers=4)
+    ct = fx["bwd_ct"]
+    nb = ct.shape[0]
+    announce(f"autograd ln|psi|-only loss, workload {idx} B={nb}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    r = torch.tensor(fx["walkers"][:nb], dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda", requires_grad=True)
+    la, _, _, _, _ = pn.paulinet_eval(ctx, r, th, pn.PN_PREC_FP64)
+    (torch.tensor(ct, device="cuda") * la).sum().backward()
+    torch.cuda.synchronize()
+    got, ref = th.grad.cpu().numpy(), fx["bwd_grad"]
+    assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
+    used = max(t.numel() for t in ctx._ws.values())
+    assert used == ctx.workspace_bytes(nb, pn.PN_PREC_FP64, full=False)
+    assert used < ctx.workspace_bytes(nb, pn.PN_PREC_FP64, full=True)
