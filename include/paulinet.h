@@ -115,6 +115,20 @@ typedef struct {
 #define PN_NET_NO_JASTROW 1
 #define PN_NET_NO_BACKFLOW 2
 
+/* Determinant path of the forward evaluation.  When every determinant of
+ * the expansion differs from the first one in at most 4 orbitals per spin
+ * (single, double, ... excitations; Results, eq. "ansatz": the
+ * multideterminant sum), pn_eval evaluates the expansion through one LU of
+ * the first determinant per spin: det A_p = det A_0 det(Theta[v][h]) with
+ * the excitation table Theta = Phi~ A_0^{-1}, and the coordinate derivatives
+ * through T_a A_0^{-1} (one product per spin and coordinate instead of one
+ * per determinant).  This is exact up to rounding; walkers whose first
+ * determinant is singular or small against another member (ratio above
+ * 1e4) are evaluated member by member instead.  PN_DET_DIRECT in
+ * pn_net_desc.flags forces the member-by-member path for every walker.
+ * The adjoints always take the member-by-member path. */
+#define PN_DET_DIRECT 4
+
 /* Create a context: validates shapes, builds the pair and determinant
  * tables and the nuclear-cusp polynomials on the host, copies them to the
  * current device.  *out is NULL on error. */
@@ -157,6 +171,23 @@ pn_status pn_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision 
  * inputs of the tangent pass and per-chunk cotangent tables per walker
  * tile); never less than pn_workspace_bytes. */
 pn_status pn_workspace_bytes_full(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+
+/* How a call with n_walkers walkers is carried out: walkers per internal
+ * tile, coordinates per chunk of the tangent (derivative) pass, number of
+ * chunks, whether the determinants take the low-rank path (PN_DET_DIRECT),
+ * and the workspace bytes of that call.  kind: 0 = pn_eval, 1 =
+ * pn_eval_backward with only ct_logabs (value-path adjoint), 2 =
+ * pn_eval_backward with coordinate cotangents (full adjoint).  [host] out. */
+typedef struct {
+  int64_t tile_walkers;
+  int32_t chunk_coords;
+  int32_t n_chunks;
+  int32_t lowrank;
+  int32_t reserved;
+  size_t workspace_bytes;
+} pn_plan_info;
+
+pn_status pn_eval_plan(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, int32_t kind, pn_plan_info* out);
 
 /* Forward evaluation (the hot path).
  *   r       [B][n_elec][3] FP64 walker positions
@@ -288,6 +319,38 @@ typedef struct {
 pn_status pn_vmc_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
 pn_status pn_vmc_step(const pn_ctx* ctx, hipStream_t stream, const pn_vmc_job* job, pn_precision prec,
                       const pn_vmc_hparams* hp, void* ws, size_t ws_bytes);
+
+/* ---- continuous batching: one step of every active job ------------------
+ * Device bytes of a job, for admission by memory: `resident` covers what
+ * the job keeps between steps (walkers, parameters, both AdamW moments,
+ * E_loc and the 8 statistics, all FP64), `scratch` the per-step workspace
+ * (pn_vmc_workspace_bytes).  [host] outputs. */
+pn_status pn_job_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* resident,
+                       size_t* scratch);
+
+/* One active job of a serving step: its context (system and network shape),
+ * its state (pn_vmc_job: walkers, parameters, moments, E_loc, statistics,
+ * seed and step counter t) and its workspace of pn_vmc_workspace_bytes. */
+typedef struct {
+  const pn_ctx* ctx;
+  pn_vmc_job job;
+  void* ws;
+  size_t ws_bytes;
+} pn_job_slot;
+
+/* One VMC step (the seven parts listed under pn_vmc_step) of every job in
+ * slots[0 .. n_slots-1] ([host] array; jobs of different systems, electron
+ * counts and walker counts), as one launch sequence on `stream`: for each
+ * part, the wavefunction evaluations run job by job and the proposal,
+ * acceptance, clipping, gradient clearing and AdamW run as one launch over
+ * all slots (16 slots per launch), with every slot's pointers passed in the
+ * kernel arguments (nothing is allocated or copied).  Each job's results
+ * equal those of pn_vmc_step on the same state bit for bit, whatever the
+ * other slots hold; the caller advances each job's `step` afterwards.  Every
+ * slot is validated before anything is enqueued.  Slots must not share
+ * state or workspace buffers. */
+pn_status pn_serve_step(hipStream_t stream, const pn_job_slot* slots, int32_t n_slots, pn_precision prec,
+                        const pn_vmc_hparams* hp);
 
 /* Per-stage kernel timing, for profiling.  When enabled, pn_eval records
  * a HIP event before and after each of its stages on the call's stream.

@@ -15,7 +15,9 @@ from ._lib import (  # noqa: F401
     library_path,
     langevin_run,
     load_library,
+    job_bytes,
     paulinet_eval,
+    serve_step,
     vmc_step,
     vmc_workspace_bytes,
 )

@@ -56,6 +56,15 @@ class pn_net_desc(ctypes.Structure):
     ]
 
 
+class pn_plan_info(ctypes.Structure):
+    _fields_ = [("tile_walkers", ctypes.c_int64), ("chunk_coords", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+                ("lowrank", ctypes.c_int32), ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t)]
+
+
+PN_DET_DIRECT = 4
+PLAN_EVAL, PLAN_VALUE_ADJOINT, PLAN_FULL_ADJOINT = 0, 1, 2
+
+
 class pn_param_entry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("offset", ctypes.c_int64), ("ndim", ctypes.c_int32),
                 ("shape", ctypes.c_int32 * 2)]
@@ -82,6 +91,10 @@ class pn_vmc_job(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("step", ctypes.c_int64),
     ]
+
+
+class pn_job_slot(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("job", pn_vmc_job), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 DEFAULT_HPARAMS = dict(sigma=0.3, lr0=0.01, t0=200.0, clip_q=5.0, beta1=0.9, beta2=0.999, eps=1e-8,
@@ -142,6 +155,12 @@ def load_library():
     lib.pn_vmc_step.argtypes = [vp, vp, ctypes.POINTER(pn_vmc_job), i32, ctypes.POINTER(pn_vmc_hparams), vp,
                                 ctypes.c_size_t]
     lib.pn_vmc_step.restype = i32
+    lib.pn_job_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_job_bytes.restype = i32
+    lib.pn_serve_step.argtypes = [vp, ctypes.POINTER(pn_job_slot), i32, i32, ctypes.POINTER(pn_vmc_hparams)]
+    lib.pn_serve_step.restype = i32
+    lib.pn_eval_plan.argtypes = [vp, i64, i32, i32, ctypes.POINTER(pn_plan_info)]
+    lib.pn_eval_plan.restype = i32
     lib.pn_status_string.argtypes = [i32]
     lib.pn_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -237,6 +256,16 @@ class PauliNetContext:
         arr = (pn_param_entry * n.value)()
         _check(self._lib.pn_param_layout(self._ctx, arr, n.value, ctypes.byref(n)), "pn_param_layout")
         return [(e.name.decode(), int(e.offset), tuple(int(e.shape[k]) for k in range(e.ndim))) for e in arr]
+
+    def plan(self, n_walkers, prec=PN_PREC_FP64, kind=PLAN_EVAL):
+        """How the library carries out a call: tile, tangent chunk, number of
+        chunks, determinant path, workspace bytes."""
+        info = pn_plan_info()
+        _check(self._lib.pn_eval_plan(self._ctx, int(n_walkers), int(prec), int(kind), ctypes.byref(info)),
+               "pn_eval_plan")
+        return {"tile_walkers": int(info.tile_walkers), "chunk_coords": int(info.chunk_coords),
+                "n_chunks": int(info.n_chunks), "lowrank": bool(info.lowrank),
+                "workspace_bytes": int(info.workspace_bytes)}
 
     def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64, full=False):
         """Workspace bytes; full=True also covers the full adjoint."""
@@ -397,14 +426,16 @@ def vmc_workspace_bytes(ctx, n_walkers, prec):
     return int(b.value)
 
 
-def vmc_step(ctx, state, prec, hparams=None, stream=None):
-    """One VMC step of a job on `stream` (torch stream; default current).
-    `state` holds device tensors r, params, adam_m, adam_v, eloc, stats, ws
-    and ints seed, step; the tensors are updated in place."""
+def job_bytes(ctx, n_walkers, prec):
+    """(resident, scratch) device bytes of a serving job (pn_job_bytes)."""
+    res, scr = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(ctx._lib.pn_job_bytes(ctx._ctx, int(n_walkers), int(prec), ctypes.byref(res), ctypes.byref(scr)),
+           "pn_job_bytes")
+    return int(res.value), int(scr.value)
+
+
+def _job_struct(state):
     import torch
-    hp = dict(DEFAULT_HPARAMS)
-    hp.update(hparams or {})
-    h = pn_vmc_hparams(**hp)
     j = pn_vmc_job()
     j.n_walkers = int(state["r"].shape[0])
     for k in ("r", "params", "adam_m", "adam_v", "eloc", "stats"):
@@ -414,6 +445,40 @@ def vmc_step(ctx, state, prec, hparams=None, stream=None):
         setattr(j, k, t.data_ptr())
     j.seed = int(state["seed"]) & 0xFFFFFFFFFFFFFFFF
     j.step = int(state["step"])
+    return j
+
+
+def serve_step(states, prec, hparams=None, stream=None):
+    """One VMC step of every job in `states` (each a dict as for vmc_step,
+    with its PauliNetContext under "ctx") as one pn_serve_step launch
+    sequence on `stream`.  The caller advances each state's "step"."""
+    import torch
+    if not states:
+        return
+    hp = dict(DEFAULT_HPARAMS)
+    hp.update(hparams or {})
+    h = pn_vmc_hparams(**hp)
+    arr = (pn_job_slot * len(states))()
+    for k, st in enumerate(states):
+        arr[k].ctx = st["ctx"]._ctx
+        arr[k].job = _job_struct(st)
+        arr[k].ws = st["ws"].data_ptr()
+        arr[k].ws_bytes = st["ws"].numel()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    lib = states[0]["ctx"]._lib
+    _check(lib.pn_serve_step(ctypes.c_void_p(s.cuda_stream), arr, len(states), int(prec), ctypes.byref(h)),
+           "pn_serve_step")
+
+
+def vmc_step(ctx, state, prec, hparams=None, stream=None):
+    """One VMC step of a job on `stream` (torch stream; default current).
+    `state` holds device tensors r, params, adam_m, adam_v, eloc, stats, ws
+    and ints seed, step; the tensors are updated in place."""
+    import torch
+    hp = dict(DEFAULT_HPARAMS)
+    hp.update(hparams or {})
+    h = pn_vmc_hparams(**hp)
+    j = _job_struct(state)
     st = stream if stream is not None else torch.cuda.current_stream()
     ws = state["ws"]
     _check(ctx._lib.pn_vmc_step(ctx._ctx, ctypes.c_void_p(st.cuda_stream), ctypes.byref(j), int(prec),

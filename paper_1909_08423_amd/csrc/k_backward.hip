@@ -43,7 +43,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
                                                       TN* __restrict__ gslot, int64_t n_params,
                                                       const double* __restrict__ ctfpart, int n_chunks,
                                                       const TN* __restrict__ cthv, const TN* __restrict__ ctkc,
-                                                      const TN* __restrict__ ctec) {
+                                                      const TN* __restrict__ ctec, TN* __restrict__ arena,
+                                                      int64_t arena_elems) {
   extern __shared__ __align__(16) char smem[];
   const int N = d.N, DX = d.DX, DZ = d.DZ, M = d.M, L = d.L, NU = d.n_up;
   const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDM = ld_pad<TN>((M + 15) & ~15);
@@ -53,7 +54,9 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
   TN* cw = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));  // [WB]
   TN* X = cw + ((WB + 3) & ~3);                                 // [RW][LDX]
   TN* CX = X + RW * LDX;                                        // [RW][LDX]
-  TN* UN = CX + RW * LDX;                                       // union region
+  // union region (heads, then layers): in LDS, or in this block's part of a
+  // global arena when it does not fit beside X and CX
+  TN* UN = arena ? arena + (size_t)blockIdx.x * arena_elems : CX + RW * LDX;
   // heads view
   TN* A = UN;                  // [RW][LDX]
   TN* B = A + RW * LDX;        // [RW][LDX]
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_net(Dims d, DevTables t, int64
 //   ct u  = ct a0 s + ct a1 s' ud + ct a2 (s' u2 + s'' (d ud)^2)
 //   ct ud = ct a1 s + 2 ct a2 s' d (d ud),   ct u2 = ct a2 s
 //   dW1 += e^T ct u + (e'/d)^T ct ud + e''^T ct u2,  db1 += ct u.
-template <typename TN, bool JETS>
+template <typename TN, bool JETS, int PT>
 __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, int64_t nw, const double* __restrict__ r,
                                                          const TN* __restrict__ P, ParamLayout pl,
                                                          const TN* __restrict__ ctw, const TN* __restrict__ ctww,
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
   const int layer = blockIdx.y / 3, ch = blockIdx.y % 3;
   const int K = d.K, DZ = d.DZ, L = d.L;
   const int LDK = ld_pad<TN>(K), LDZ = ld_pad<TN>(DZ);
-  const int PT = kFiltRows;
+  constexpr int RPG = PT / 4;  // rows of a tile per lane group of the MFMA reduction
   const int p_lo = ch == 0 ? 0 : (ch == 1 ? n_same : d.n_ee);
   const int p_hi = ch == 0 ? n_same : (ch == 1 ? d.n_ee : d.n_pairs);
   const int np = p_hi - p_lo;
@@ -358,8 +361,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
   const int fsz = K * DZ + DZ + DZ * DZ + DZ;
   // weight gradients dW1 = sum_k E_k^T CU_k and dW2 = sum_k U_k^T CW_k on
   // the matrix cores: every wavefront keeps its 16 x 16 output tiles in
-  // registers across all row tiles; the reduction runs over the kFiltRows =
-  // 32 rows of a tile.
+  // registers across all row tiles; the reduction runs over the PT rows of
+  // a tile (32, or 16 where 32 would exceed the LDS).
   typedef typename MfmaTile<TN>::acc_t acc_t;
   constexpr int kMaxT = 8;  // tiles per wavefront: (K/16 + DZ/16) * DZ/16 <= 32
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
@@ -486,13 +489,13 @@ __global__ __launch_bounds__(kThreads) void k_bwd_filter(Dims d, DevTables t, in
             a0 = ((tt - nt1) / nz) * 16;
             b0 = ((tt - nt1) % nz) * 16;
           }
-          TN af[8], bf[8];
+          TN af[RPG], bf[RPG];
 #pragma unroll
-          for (int s2 = 0; s2 < 8; ++s2) {
-            af[s2] = X[(g * 8 + s2) * ldx2 + a0 + c16];
-            bf[s2] = Y[(g * 8 + s2) * LDZ + b0 + c16];
+          for (int s2 = 0; s2 < RPG; ++s2) {
+            af[s2] = X[(g * RPG + s2) * ldx2 + a0 + c16];
+            bf[s2] = Y[(g * RPG + s2) * LDZ + b0 + c16];
           }
-          accs[k] = MfmaChain<TN, 8>::run(af, bf, accs[k], false);
+          accs[k] = MfmaChain<TN, RPG>::run(af, bf, accs[k], false);
         }
       }
     }
@@ -550,15 +553,23 @@ __global__ __launch_bounds__(kThreads) void k_bwd_reduce(Dims d, ParamLayout pl,
 
 }  // namespace
 
-// walkers per group of k_bwd_net, chosen from the LDS budget
+// elements of k_bwd_net's union region (head buffers, or layer buffers)
 template <typename TN>
-static size_t bwd_net_lds(const Dims& d, int WB) {
+static size_t bwd_net_union(const Dims& d, int WB) {
   const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDM = ld_pad<TN>((d.M + 15) & ~15);
   const size_t RW = (size_t)WB * d.N;
   const size_t heads = 3 * RW * LDX + RW * LDM + 6 * (size_t)WB * LDX;  // kappa buffers, then the eta ones
   const size_t layers = 4 * RW * LDZ;
+  return std::max(heads, layers);
+}
+
+// LDS of k_bwd_net; with `arena` the union region lives in global memory
+template <typename TN>
+static size_t bwd_net_lds(const Dims& d, int WB, bool arena = false) {
+  const int LDX = ld_pad<TN>(d.DX);
+  const size_t RW = (size_t)WB * d.N;
   return (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) +
-         ((size_t)((WB + 3) & ~3) + 2 * RW * LDX + std::max(heads, layers)) * sizeof(TN);
+         ((size_t)((WB + 3) & ~3) + 2 * RW * LDX + (arena ? 0 : bwd_net_union<TN>(d, WB))) * sizeof(TN);
 }
 
 template <typename TN>
@@ -566,6 +577,24 @@ static int bwd_wb(const Dims& d) {
   int wb = std::max(1, 64 / d.N);
   while (wb > 1 && bwd_net_lds<TN>(d, wb) > 80 * 1024) --wb;
   return wb;
+}
+
+// k_bwd_net keeps its union region in a global arena when the whole block
+// does not fit in LDS (the 30-electron system in FP64)
+template <typename TN>
+static bool bwd_net_arena(const Dims& d) {
+  return bwd_net_lds<TN>(d, bwd_wb<TN>(d)) > 160 * 1024;
+}
+
+// rows per tile of k_bwd_filter: 32, or 16 when 32 exceed the LDS
+static int bwd_filter_rows(const Dims& d, bool fp32, bool full) {
+  const int nj = full ? 3 : 1;
+  const size_t tn = fp32 ? sizeof(float) : sizeof(double);
+  const size_t ldk = fp32 ? ld_pad<float>(d.K) : ld_pad<double>(d.K);
+  const size_t ldz = fp32 ? ld_pad<float>(d.DZ) : ld_pad<double>(d.DZ);
+  for (int pt = kFiltRows; pt >= 16; pt /= 2)
+    if (pt * sizeof(double) + (size_t)nj * pt * (ldk + 3 * ldz) * tn <= 160 * 1024) return pt;
+  return 16;
 }
 
 static size_t filt_fsz(const Dims& d) { return (size_t)d.K * d.DZ + d.DZ + (size_t)d.DZ * d.DZ + d.DZ; }
@@ -577,13 +606,18 @@ size_t backward_scratch_bytes(const pn_ctx* c, int64_t tile, bool fp32) {
   b += (size_t)kSlotsNet * c->pl.total * tn;                       // net slots
   b += (size_t)kSlotsFilter * d.L * 3 * filt_fsz(d) * tn;          // filter slots
   b += (size_t)tile * d.L * d.n_pairs * d.DZ * tn;                 // filter cotangents
+  const bool arena = fp32 ? bwd_net_arena<float>(d) : bwd_net_arena<double>(d);
+  if (arena)
+    b += (size_t)kSlotsNet * (fp32 ? bwd_net_union<float>(d, bwd_wb<float>(d)) : bwd_net_union<double>(d, bwd_wb<double>(d))) *
+         tn;
   return b + 1024;
 }
 
 bool backward_supported(const pn_ctx* c, bool fp32) {
   const Dims& d = c->d;
   if ((d.K / 16 + d.DZ / 16) * (d.DZ / 16) > 8 * (kThreads / 64)) return false;  // accumulator tiles per wave
-  size_t lds = fp32 ? bwd_net_lds<float>(d, bwd_wb<float>(d)) : bwd_net_lds<double>(d, bwd_wb<double>(d));
+  size_t lds = fp32 ? bwd_net_lds<float>(d, bwd_wb<float>(d), bwd_net_arena<float>(d))
+                    : bwd_net_lds<double>(d, bwd_wb<double>(d), bwd_net_arena<double>(d));
   return lds <= 160 * 1024;
 }
 
@@ -596,7 +630,10 @@ static void run_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const doubl
   TN* fslot = gslot + (size_t)kSlotsNet * np;
   TN* ctw = fslot + (size_t)kSlotsFilter * d.L * 3 * filt_fsz(d);
   const int WB = bwd_wb<TN>(d);
-  const size_t lds = bwd_net_lds<TN>(d, WB);
+  const bool use_arena = bwd_net_arena<TN>(d);
+  TN* arena = use_arena ? ctw + (size_t)L.tile * d.L * d.n_pairs * d.DZ : nullptr;
+  const int64_t arena_elems = use_arena ? (int64_t)bwd_net_union<TN>(d, WB) : 0;
+  const size_t lds = bwd_net_lds<TN>(d, WB, use_arena);
   if (lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bwd_net<TN>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -609,14 +646,15 @@ static void run_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const doubl
                      ctw, gslot, np, full ? reinterpret_cast<const double*>(ws + L.ctfpart) : nullptr, L.n_chunks,
                      full ? reinterpret_cast<const TN*>(ws + L.cthv) : nullptr,
                      full ? reinterpret_cast<const TN*>(ws + L.ctkc) : nullptr,
-                     full ? reinterpret_cast<const TN*>(ws + L.ctec) : nullptr);
+                     full ? reinterpret_cast<const TN*>(ws + L.ctec) : nullptr, arena, arena_elems);
   const int n_same = d.n_up * (d.n_up - 1) / 2 + d.n_dn * (d.n_dn - 1) / 2;
   const int64_t max_np = std::max<int64_t>(std::max(n_same, d.n_ee - n_same), (int64_t)d.N * d.NN);
-  const int nb_f = (int)std::min<int64_t>((nw * max_np + kFiltRows - 1) / kFiltRows, kSlotsFilter);
+  const int PT = bwd_filter_rows(d, sizeof(TN) == sizeof(float), full);
+  const int nb_f = (int)std::min<int64_t>((nw * max_np + PT - 1) / PT, kSlotsFilter);
   const int nj = full ? 3 : 1;
-  const size_t lds_f = kFiltRows * sizeof(double) +
-                       (size_t)nj * kFiltRows * (ld_pad<TN>(d.K) + 3 * ld_pad<TN>(d.DZ)) * sizeof(TN);
-  auto filt_kernel = full ? &k_bwd_filter<TN, true> : &k_bwd_filter<TN, false>;
+  const size_t lds_f = PT * sizeof(double) + (size_t)nj * PT * (ld_pad<TN>(d.K) + 3 * ld_pad<TN>(d.DZ)) * sizeof(TN);
+  auto filt_kernel = PT == 32 ? (full ? &k_bwd_filter<TN, true, 32> : &k_bwd_filter<TN, false, 32>)
+                              : (full ? &k_bwd_filter<TN, true, 16> : &k_bwd_filter<TN, false, 16>);
   if (lds_f > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(filt_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_f);
@@ -644,7 +682,8 @@ size_t backward_filter_lds_bytes(const Dims& d, bool fp32, bool full) {
   const size_t tn = fp32 ? sizeof(float) : sizeof(double);
   const size_t ldk = fp32 ? ld_pad<float>(d.K) : ld_pad<double>(d.K);
   const size_t ldz = fp32 ? ld_pad<float>(d.DZ) : ld_pad<double>(d.DZ);
-  return kFiltRows * sizeof(double) + (size_t)nj * kFiltRows * (ldk + 3 * ldz) * tn;
+  const int pt = bwd_filter_rows(d, fp32, full);
+  return pt * sizeof(double) + (size_t)nj * pt * (ldk + 3 * ldz) * tn;
 }
 
 }  // namespace pn

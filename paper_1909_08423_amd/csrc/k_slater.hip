@@ -42,21 +42,25 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kWaves = kThreads / 64;
 
+// With wlist set, the (determinant, spin) matrices of the listed walkers
+// only (*wcount of them), taken by a grid-stride loop.
 __global__ __launch_bounds__(kThreads) void k_slater_value(Dims d, DevTables t, int64_t nw,
                                                            const double* __restrict__ phi,
                                                            const double* __restrict__ fval,
-                                                           double* __restrict__ ginv, double* __restrict__ ldet) {
+                                                           double* __restrict__ ginv, double* __restrict__ ldet,
+                                                           const int* __restrict__ wlist,
+                                                           const int* __restrict__ wcount) {
   extern __shared__ __align__(16) char smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int NM = max(d.n_up, d.n_dn), LD = NM + 1;
   double* A = reinterpret_cast<double*>(smem) + (size_t)wv * 2 * NM * LD;
   double* X = A + NM * LD;
   int* perm = reinterpret_cast<int*>(reinterpret_cast<double*>(smem) + (size_t)kWaves * 2 * NM * LD) + wv * kMaxSpin;
-  const int64_t mat = (int64_t)blockIdx.x * kWaves + wv;
-  if (mat >= nw * d.P * 2) return;
+  const int64_t nmat = (wlist ? (int64_t)*wcount : nw) * d.P * 2;
+  for (int64_t mat = (int64_t)blockIdx.x * kWaves + wv; mat < nmat; mat += (int64_t)gridDim.x * kWaves) {
   const int spin = (int)(mat % 2);
   const int p = (int)((mat / 2) % d.P);
-  const int64_t w = mat / (2 * d.P);
+  const int64_t w = wlist ? (int64_t)wlist[mat / (2 * d.P)] : mat / (2 * d.P);
   const int n = spin == 0 ? d.n_up : d.n_dn;
   const int e0 = spin == 0 ? 0 : d.n_up;
   const int* occ = spin == 0 ? t.det_up + p * d.n_up : t.det_dn + p * d.n_dn;
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_slater_value(Dims d, DevTables t, 
       ld[0] = 0.0;
       ld[1] = 1.0;
     }
-    return;
+    continue;
   }
   const double* ph = phi + w * N * M * 7;
   const double* fv = fval + w * N * M;
@@ -134,7 +138,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_value(Dims d, DevTables t, 
       ld[1] = 0.0;
     }
     for (int q = lane; q < n * n; q += 64) G[q] = 0.0;
-    return;
+    wave_sync();
+    continue;
   }
   if (lane == 0) {
     ld[0] = logabs;
@@ -156,6 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_value(Dims d, DevTables t, 
   }
   wave_sync();
   for (int q = lane; q < n * n; q += 64) G[q] = X[(q / n) * LD + q % n];
+  wave_sync();
+  }
 }
 
 // Small determinants (n <= NMAX): one lane per (walker, determinant, spin).
@@ -167,12 +174,15 @@ template <int NMAX>
 __global__ __launch_bounds__(kThreads) void k_slater_value_lane(Dims d, DevTables t, int64_t nw,
                                                                 const double* __restrict__ phi,
                                                                 const double* __restrict__ fval,
-                                                                double* __restrict__ ginv, double* __restrict__ ldet) {
-  const int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (mat >= nw * d.P * 2) return;
+                                                                double* __restrict__ ginv, double* __restrict__ ldet,
+                                                                const int* __restrict__ wlist,
+                                                                const int* __restrict__ wcount) {
+  const int64_t nmat = (wlist ? (int64_t)*wcount : nw) * d.P * 2;
+  for (int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mat < nmat;
+       mat += (int64_t)gridDim.x * blockDim.x) {
   const int spin = (int)(mat % 2);
   const int p = (int)((mat / 2) % d.P);
-  const int64_t w = mat / (2 * d.P);
+  const int64_t w = wlist ? (int64_t)wlist[mat / (2 * d.P)] : mat / (2 * d.P);
   const int n = spin == 0 ? d.n_up : d.n_dn;
   const int e0 = spin == 0 ? 0 : d.n_up;
   const int* occ = spin == 0 ? t.det_up + p * d.n_up : t.det_dn + p * d.n_dn;
@@ -183,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_slater_value_lane(Dims d, DevTable
   if (n == 0) {
     ld[0] = 0.0;
     ld[1] = 1.0;
-    return;
+    continue;
   }
   const double* ph = phi + w * N * M * 7;
   const double* fv = fval + w * N * M;
@@ -276,6 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_slater_value_lane(Dims d, DevTable
 #pragma unroll
     for (int k = 0; k < NMAX; ++k)
       if (i < n && k < n) G[i * n + k] = singular ? 0.0 : a[i][k];
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_combine_value(Dims d, DevTables t, int64_t nw,
@@ -331,11 +342,17 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
                                                              const double* __restrict__ ginv,
                                                              const double* __restrict__ wdet,
                                                              double* __restrict__ grad, double* __restrict__ partial,
-                                                             double* __restrict__ detres) {
+                                                             double* __restrict__ detres,
+                                                             const int* __restrict__ wlist,
+                                                             const int* __restrict__ wcount) {
   extern __shared__ __align__(16) char smem[];
-  const int64_t task = blockIdx.x;
-  const int64_t w = task / n_chunks;
-  const int chunk = (int)(task % n_chunks);
+  // one (walker, chunk) task per iteration; with wlist set only the listed
+  // walkers' tasks (*wcount walkers), taken by a grid-stride loop
+  const int64_t ntask = (wlist ? (int64_t)*wcount : nw) * n_chunks;
+  for (int64_t it = blockIdx.x; it < ntask; it += gridDim.x) {
+  const int64_t w = wlist ? (int64_t)wlist[it / n_chunks] : it / n_chunks;
+  const int chunk = (int)(it % n_chunks);
+  const int64_t task = w * n_chunks + chunk;
   const int N = d.N, M = d.M, P = d.P;
   const int a0 = chunk * T, Tc = min(T, 3 * N - a0), C = Tc + 1, LC = Tc;
   const int NM = max(max(d.n_up, d.n_dn), 1);
@@ -475,6 +492,8 @@ __global__ __launch_bounds__(kThreads) void k_slater_tangent(Dims d, DevTables t
       partial[(w * n_chunks + chunk) * 2 + 1] = sq_part;
     }
   }
+  __syncthreads();  // the next task overwrites the tables
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(Dims d, int64_t nw, int n_chunks, const double* __restrict__ geo,
@@ -493,23 +512,37 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Dims d, int64_t nw, int n
 
 }  // namespace
 
+// LU of every (walker, determinant, spin) matrix of the dims `d` (which may
+// restrict the expansion to its first determinant), written to G / ld; with
+// a walker list, the listed walkers only, on a fixed grid.
+void launch_slater_lu(const pn_ctx* c, const Dims& d, hipStream_t s, int64_t nw, char* ws, const WsLayout& L,
+                      double* G, double* ld, const int* wlist, const int* wcount, int64_t nb_lane, int64_t nb_wave) {
+  const int NM = std::max(d.n_up, d.n_dn);
+  if (NM <= 8) {
+    auto kern = NM <= 4 ? &k_slater_value_lane<4> : (NM <= 6 ? &k_slater_value_lane<6> : &k_slater_value_lane<8>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)std::max<int64_t>(nb_lane, 1)), dim3(kThreads), 0, s, d, c->t, nw,
+                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval), G, ld,
+                       wlist, wcount);
+  } else {
+    size_t lds = (size_t)kWaves * 2 * NM * (NM + 1) * sizeof(double) + kWaves * kMaxSpin * sizeof(int);
+    hipLaunchKernelGGL(k_slater_value, dim3((unsigned)std::max<int64_t>(nb_wave, 1)), dim3(kThreads), lds, s, d, c->t,
+                       nw, reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval), G,
+                       ld, wlist, wcount);
+  }
+}
+
 void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* logabs,
                          double* sign) {
   const Dims& d = c->d;
-  const int NM = std::max(d.n_up, d.n_dn);
   int64_t nmat = nw * d.P * 2;
-  if (NM <= 8) {
-    auto kern = NM <= 4 ? &k_slater_value_lane<4> : (NM <= 6 ? &k_slater_value_lane<6> : &k_slater_value_lane<8>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)((nmat + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d, c->t, nw,
-                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
-                       reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet));
-  } else {
-    size_t lds = (size_t)kWaves * 2 * NM * (NM + 1) * sizeof(double) + kWaves * kMaxSpin * sizeof(int);
-    int64_t nb = (nmat + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(k_slater_value, dim3((unsigned)nb), dim3(kThreads), lds, s, d, c->t, nw,
-                       reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
-                       reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet));
-  }
+  launch_slater_lu(c, d, s, nw, ws, L, reinterpret_cast<double*>(ws + L.ginv), reinterpret_cast<double*>(ws + L.ldet),
+                   nullptr, nullptr, (nmat + kThreads - 1) / kThreads, (nmat + kWaves - 1) / kWaves);
+  launch_combine_value(c, s, nw, ws, L, logabs, sign);
+}
+
+void launch_combine_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* logabs,
+                          double* sign) {
+  const Dims& d = c->d;
   int64_t nb2 = (nw + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_combine_value, dim3((unsigned)nb2), dim3(kThreads), 0, s, d, c->t, nw,
                      reinterpret_cast<const double*>(ws + L.geo), reinterpret_cast<const double*>(ws + L.jval),
@@ -524,21 +557,23 @@ size_t slater_tangent_lds_bytes(const Dims& d, int T) {
 }
 
 void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws, const WsLayout& L,
-                           double* grad, double* detres) {
+                           double* grad, double* detres, const int* wlist, const int* wcount) {
   const Dims& d = c->d;
   (void)r;
   size_t lds = slater_tangent_lds_bytes(d, L.T);
   const int NM = std::max(d.n_up, d.n_dn);
+  // a listed subset (walkers the low-rank path hands back) runs on a fixed grid
+  const int64_t nb = wlist ? std::min<int64_t>(nw * L.n_chunks, kListGrid) : nw * L.n_chunks;
   auto go = [&](auto kern) {
     if (lds > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)(nw * L.n_chunks)), dim3(kThreads), lds, s, d, c->t, nw, L.T,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreads), lds, s, d, c->t, nw, L.T,
                        L.n_chunks, reinterpret_cast<const double*>(ws + L.geo),
                        reinterpret_cast<const double*>(ws + L.phi), reinterpret_cast<const double*>(ws + L.fval),
                        reinterpret_cast<const double*>(ws + L.ftan), reinterpret_cast<const double*>(ws + L.jtan),
                        reinterpret_cast<const double*>(ws + L.ginv), reinterpret_cast<const double*>(ws + L.wdet),
-                       grad, reinterpret_cast<double*>(ws + L.partial), detres);
+                       grad, reinterpret_cast<double*>(ws + L.partial), detres, wlist, wcount);
   };
   if (NM <= 8)
     go(&k_slater_tangent<8>);

@@ -131,9 +131,12 @@ enum { kPlanForward = 0, kPlanValueAdjoint = 1, kPlanFullAdjoint = 2 };
 
 // chunk size of the full adjoint: the largest T in 1..6 whose tangent-adjoint
 // block keeps its row buffers in LDS; when none fits, the row buffers go to a
-// per-block global arena and T is the largest whose small tables fit
+// per-block global arena and T is the largest whose small tables fit.  The
+// forward tangent pass runs with the same chunks, so its block must fit too.
 void plan_full_adjoint(const Dims& d, bool fp64, WsLayout& L) {
   auto lds = [&](int T, bool ga) {
+    const size_t fwd = fp64 ? tangent_lds_bytes<double>(d, T, false) : tangent_lds_bytes<float>(d, T, false);
+    if (fwd > kLdsMax) return fwd;
     return fp64 ? tangent_adj_lds_bytes<double>(d, T, ga) : tangent_adj_lds_bytes<float>(d, T, ga);
   };
   const int ncoord = 3 * d.N;
@@ -220,6 +223,11 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
          (fp64 ? filter_lds_bytes<double>(d, L.filt_rows) : filter_lds_bytes<float>(d, L.filt_rows)) > 64 * 1024)
     L.filt_rows /= 2;
   L.lds_filter = fp64 ? filter_lds_bytes<double>(d, L.filt_rows) : filter_lds_bytes<float>(d, L.filt_rows);
+  // determinants of the forward pass through one LU per spin when the
+  // expansion allows it (and the caller did not ask for the direct path)
+  L.lowrank = mode == kPlanForward && d.lr && !(d.flags & PN_DET_DIRECT);
+  L.lds_lr = L.lowrank ? lowrank_tangent_lds_bytes(d, L.T) : 0;
+  if (L.lds_lr > kLdsMax) L.lowrank = false;
 
   const int N = d.N, M = d.M, P = d.P, Tp = L.T + 1;
   const size_t gsz = (size_t)d.n_up * d.n_up + (size_t)d.n_dn * d.n_dn;
@@ -236,6 +244,9 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
     b += (size_t)L.n_chunks * N * Tp * M * 8 + (size_t)L.n_chunks * Tp * 8 + (size_t)L.n_chunks * 2 * 8;
     b += (size_t)N * 3 * 8;
     if (with_bwd) b += (size_t)(d.L + 1) * N * d.DX * tn;
+    if (L.lowrank)
+      b += (gsz + 4 + (size_t)d.nv[0] * d.n_up + (size_t)d.nv[1] * d.n_dn + (size_t)P * 2 * kMaxExc * kMaxExc) * 8 +
+           3 * 4;
     if (full) {
       const size_t nc = L.n_chunks, N3 = 3 * N;
       b += nc * d.L * N * Tp * d.DX * tn;                     // xsave
@@ -279,6 +290,14 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
   if (backward) {
     L.xval = region((size_t)tile * (d.L + 1) * N * d.DX * tn);
     L.gpart = region(backward_scratch_bytes(c, tile, !fp64));
+  }
+  if (L.lowrank) {
+    L.g0 = region((size_t)tile * gsz * 8);
+    L.ld0 = region((size_t)tile * 4 * 8);
+    L.theta = region((size_t)tile * ((size_t)d.nv[0] * d.n_up + (size_t)d.nv[1] * d.n_dn) * 8);
+    L.dinv = region((size_t)tile * P * 2 * kMaxExc * kMaxExc * 8);
+    L.lrflag = region((size_t)tile * 2 * 4);
+    L.lrlist = region((size_t)(tile + 1) * 4);
   }
   if (full) {
     const size_t nc = L.n_chunks, N3 = 3 * N;
@@ -366,7 +385,7 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
       sys->n_up < 0 || sys->n_down < 0 || sys->n_up + sys->n_down < 1 || (sys->n_up > 0 && !sys->det_up) ||
       (sys->n_down > 0 && !sys->det_down) || !(sys->cusp_radius >= 0))
     return PN_ERR_INVALID_ARG;
-  if (net->flags & ~(PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) return PN_ERR_INVALID_ARG;
+  if (net->flags & ~(PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW | PN_DET_DIRECT)) return PN_ERR_INVALID_ARG;
   if (net->n_feat < 1 || net->dim_x < 1 || net->dim_z < 1 || net->n_layers < 1 || !(net->feat_cutoff > 0))
     return PN_ERR_INVALID_ARG;
   const int N = sys->n_up + sys->n_down;
@@ -544,6 +563,64 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
         pidx[(size_t)j * N + i] = p;
       }
 
+  // the expansion as excitations of its first determinant (low-rank path):
+  // per (determinant, spin) the hole slots of the first determinant's rows,
+  // the particle orbitals replacing them (as rows of the spin's virtual
+  // list), and the sign of the row order
+  std::vector<int> lrk((size_t)P * 2, 0), lrh((size_t)P * 2 * kMaxExc, 0), lrp((size_t)P * 2 * kMaxExc, 0),
+      lrv((size_t)2 * M, 0);
+  std::vector<double> lrs((size_t)P * 2, 1.0);
+  int lr_ok = P >= 2 ? 1 : 0;
+  d.nv[0] = d.nv[1] = 0;
+  for (int sp = 0; sp < 2 && lr_ok; ++sp) {
+    const int n = sp == 0 ? d.n_up : d.n_dn;
+    const int* occ = sp == 0 ? du.data() : dd.data();
+    std::vector<int> slot(M, -1), vrow(M, -1);
+    for (int k = 0; k < n && lr_ok; ++k) {
+      if (slot[occ[k]] >= 0) lr_ok = 0;  // repeated orbital: the first determinant vanishes
+      slot[occ[k]] = k;
+    }
+    for (int p = 0; p < P && lr_ok; ++p) {
+      const int* op = occ + (size_t)p * n;
+      std::vector<char> in_p(M, 0);
+      for (int k = 0; k < n; ++k) {
+        if (in_p[op[k]]) lr_ok = 0;
+        in_p[op[k]] = 1;
+      }
+      std::vector<int> holes, parts;
+      for (int k = 0; k < n; ++k)
+        if (!in_p[occ[k]]) holes.push_back(k);
+      for (int k = 0; k < n; ++k)
+        if (slot[op[k]] < 0) parts.push_back(op[k]);
+      std::sort(parts.begin(), parts.end());
+      if (!lr_ok || (int)holes.size() > kMaxExc || holes.size() != parts.size()) {
+        lr_ok = 0;
+        break;
+      }
+      std::vector<int> seq(occ, occ + n);
+      for (size_t j = 0; j < holes.size(); ++j) seq[holes[j]] = parts[j];
+      int inversions = 0;
+      std::vector<int> pos(n);
+      for (int k = 0; k < n; ++k) pos[k] = (int)(std::find(seq.begin(), seq.end(), op[k]) - seq.begin());
+      for (int a = 0; a < n; ++a)
+        for (int b2 = a + 1; b2 < n; ++b2) inversions += pos[a] > pos[b2];
+      const size_t q = (size_t)p * 2 + sp;
+      lrs[q] = (inversions & 1) ? -1.0 : 1.0;
+      lrk[q] = (int)holes.size();
+      for (size_t j = 0; j < holes.size(); ++j) {
+        if (vrow[parts[j]] < 0) {
+          vrow[parts[j]] = d.nv[sp];
+          lrv[(size_t)sp * M + d.nv[sp]] = parts[j];
+          ++d.nv[sp];
+        }
+        lrh[q * kMaxExc + j] = holes[j];
+        lrp[q * kMaxExc + j] = vrow[parts[j]];
+      }
+    }
+  }
+  d.lr = lr_ok;
+  if (!lr_ok) d.nv[0] = d.nv[1] = 0;
+
   hipError_t err = hipSuccess;
   DevTables& t = c->t;
   t.nuc_xyz = dev_copy(nuc, &err);
@@ -570,6 +647,11 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   t.feat_sig2inv = dev_copy(fs, &err);
   t.pair_ij = dev_copy(pij, &err);
   t.pair_index = dev_copy(pidx, &err);
+  t.lr_k = dev_copy(lrk, &err);
+  t.lr_hole = dev_copy(lrh, &err);
+  t.lr_part = dev_copy(lrp, &err);
+  t.lr_sign = dev_copy(lrs, &err);
+  t.lr_vorb = dev_copy(lrv, &err);
   if (err != hipSuccess) {
     pn_ctx_destroy(c);
     return PN_ERR_DEVICE;
@@ -590,7 +672,8 @@ void pn_ctx_destroy(pn_ctx* c) {
   void* ptrs[] = {c->t.nuc_xyz, c->t.charge, c->t.shell_center, c->t.shell_l, c->t.shell_exp, c->t.shell_norm,
                   c->t.shell_first, c->t.mo, c->t.det_up, c->t.det_dn, c->t.ci_log, c->t.ci_sign, c->t.cusp_on,
                   c->t.cusp_sign, c->t.cusp_alpha, c->t.cusp_dalpha, c->t.s_first, c->t.s_basis, c->t.s_exp, c->t.s_norm,
-                  c->t.feat_mu, c->t.feat_sig2inv, c->t.pair_ij, c->t.pair_index};
+                  c->t.feat_mu, c->t.feat_sig2inv, c->t.pair_ij, c->t.pair_index, c->t.lr_k, c->t.lr_hole,
+                  c->t.lr_part, c->t.lr_sign, c->t.lr_vorb};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -671,6 +754,19 @@ pn_status pn_workspace_bytes_full(const pn_ctx* c, int64_t nw, pn_precision prec
   return PN_OK;
 }
 
+pn_status pn_eval_plan(const pn_ctx* c, int64_t nw, pn_precision prec, int32_t kind, pn_plan_info* out) {
+  if (!c || !out || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16 || kind < 0 || kind > 2)
+    return PN_ERR_INVALID_ARG;
+  const WsLayout L = plan(c, nw, prec, kind);
+  memset(out, 0, sizeof(*out));
+  out->tile_walkers = L.tile;
+  out->chunk_coords = L.T;
+  out->n_chunks = L.n_chunks;
+  out->lowrank = L.lowrank ? 1 : 0;
+  out->workspace_bytes = L.total;
+  return PN_OK;
+}
+
 pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
                   pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc, void* ws,
                   size_t ws_bytes) {
@@ -719,7 +815,10 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
       clk.end(3);
     }
     clk.begin(4);
-    launch_slater_value(c, s, n, base, L, logabs + w0, sign + w0);
+    if (L.lowrank)
+      launch_lowrank_value(c, s, n, base, L, logabs + w0, sign + w0);
+    else
+      launch_slater_value(c, s, n, base, L, logabs + w0, sign + w0);
     clk.end(4);
     if (derivs) {
       clk.begin(5);
@@ -734,7 +833,10 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
       clk.end(5);
       double* g = grad ? grad + w0 * d.N * 3 : reinterpret_cast<double*>(base + L.adj);
       clk.begin(6);
-      launch_slater_tangent(c, s, n, rt, base, L, g);
+      if (L.lowrank)
+        launch_lowrank_tangent(c, s, n, base, L, g);
+      else
+        launch_slater_tangent(c, s, n, rt, base, L, g);
       clk.end(6);
       clk.begin(7);
       launch_finalize(c, s, n, base, L, g, lap ? lap + w0 : nullptr, eloc ? eloc + w0 : nullptr);

@@ -14,6 +14,8 @@ constexpr int kMaxElec = 64;
 constexpr int kMaxSpin = 32;
 constexpr int kMaxDet = 64;
 constexpr int kThreads = 256;
+constexpr int kMaxExc = 4;      // largest excitation rank of the low-rank determinant path
+constexpr int kListGrid = 1024;  // blocks of a grid-stride launch over a device-side walker list
 
 // Offsets (in elements) of every tensor inside the flat parameter blob.
 struct ParamLayout {
@@ -38,7 +40,12 @@ struct Dims {
   double feat_rc;
   double cusp_rc;
   double v_nn;   // nuclear repulsion, a constant of the geometry
-  int flags;     // PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW
+  int flags;     // PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW | PN_DET_DIRECT
+  // low-rank determinant path: every determinant differs from the first in
+  // at most kMaxExc orbitals per spin (lr = 1); nv[s] virtual orbitals
+  // (occupied somewhere, not in the first determinant) per spin
+  int lr;
+  int nv[2];
 };
 
 // Device-resident copies of the system tables (owned by the context).
@@ -70,6 +77,15 @@ struct DevTables {
   // pairs
   int* pair_ij;        // [n_ee][2] (i < j)
   int* pair_index;     // [N][N] unified pair index of the ee pair, -1 on the diagonal
+  // low-rank determinant path, per (determinant p, spin s) relative to the
+  // first determinant: rank k, hole slots of the first determinant's rows,
+  // particle rows (indices into the spin's virtual list), sign of the row
+  // permutation from "first determinant with holes replaced" to the listed order
+  int* lr_k;           // [P][2]
+  int* lr_hole;        // [P][2][kMaxExc]
+  int* lr_part;        // [P][2][kMaxExc]
+  double* lr_sign;     // [P][2]
+  int* lr_vorb;        // [2][M] orbital of each virtual row of spin s
 };
 
 // Workspace regions for one walker tile (byte offsets from ws base).
@@ -124,6 +140,15 @@ struct WsLayout {
   size_t ctec;         // [tile][2][2][DX]       net type
   size_t ct0;          // [tile] zeros (absent ln|psi| cotangent)
   size_t tslot;        // [kSlotsTanAdj][n_params] + global arena, net type
+  // low-rank determinant path (forward only)
+  bool lowrank;
+  size_t lds_lr;       // dynamic LDS of the low-rank tangent kernel
+  size_t g0;           // [tile][n_up^2 + n_dn^2] inverse of the first determinant per spin
+  size_t ld0;          // [tile][2][2] its (ln|det|, sign) per spin
+  size_t theta;        // [tile][nv_up n_up + nv_dn n_dn] excitation table
+  size_t dinv;         // [tile][P][2][kMaxExc^2] inverse of each determinant's minor
+  size_t lrflag;       // [tile][2] int: walker handed to the direct path
+  size_t lrlist;       // [tile + 1] int: those walkers (ascending), then their count
   size_t total;
 };
 
@@ -190,8 +215,17 @@ void launch_net_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double
                         const WsLayout& L, bool bf16, TN* xsave = nullptr);
 void launch_slater_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L,
                          double* logabs, double* sign);
+void launch_slater_lu(const pn_ctx* c, const Dims& d, hipStream_t s, int64_t nw, char* ws, const WsLayout& L,
+                      double* G, double* ld, const int* wlist, const int* wcount, int64_t nb_lane, int64_t nb_wave);
+void launch_combine_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* logabs,
+                          double* sign);
 void launch_slater_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, char* ws,
-                           const WsLayout& L, double* grad, double* detres = nullptr);
+                           const WsLayout& L, double* grad, double* detres = nullptr, const int* wlist = nullptr,
+                           const int* wcount = nullptr);
+size_t lowrank_tangent_lds_bytes(const Dims& d, int T);
+void launch_lowrank_value(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* logabs,
+                          double* sign);
+void launch_lowrank_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* grad);
 void launch_finalize(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws, const WsLayout& L, double* grad,
                      double* lap, double* eloc);
 void launch_convert_params(hipStream_t s, int64_t n, const double* src, float* dst);

@@ -28,6 +28,8 @@ CONFIG_NAMES = {
     3: "H10",
     4: "serving",
     5: "P2-like 30e diatomic",
+    6: "Z5 atom (3 up, 2 down)",
+    7: "H7 chain (4 up, 3 down)",
 }
 
 
@@ -236,7 +238,8 @@ def make_system_workload(
 
 
 def make_config(idx: int, n_walkers: Optional[int] = None) -> Workload:
-    """Workloads 1, 2, 3 and 5 (4 is the serving stream, see make_serving_jobs)."""
+    """Workloads 1, 2, 3 and 5 (4 is the serving stream, see make_serving_jobs),
+    and the unequal-spin parity cases 6 and 7."""
     seed = 1000 + idx
     if idx == 1:
         net = NetShape(16, 10.0, 32, 16, 2)
@@ -260,6 +263,20 @@ def make_config(idx: int, n_walkers: Optional[int] = None) -> Workload:
         return make_system_workload(
             "30e diatomic", [[0, 0, -2.0], [0, 0, 2.0]], [15, 15], 15, 15,
             [10, 10], [8, 8], 64, net, n_walkers or 16384, 1.0, seed, "bf16-net")
+    # parity cases with unequal spin blocks, shaped like members of the
+    # serving stream (an odd-Z atom and an odd hydrogen chain)
+    if idx == 6:
+        net = NetShape(32, 10.0, 64, 32, 3)
+        return make_system_workload(
+            "Z5 atom", [[0, 0, 0]], [5], 3, 2, [8], [6], 12,
+            net, n_walkers or 2048, 1.0, seed, "fp64|fp32-net")
+    if idx == 7:
+        net = NetShape(32, 10.0, 64, 32, 3)
+        z = (np.arange(7) - 3.0) * 1.8
+        xyz = np.stack([np.zeros(7), np.zeros(7), z], 1)
+        return make_system_workload(
+            "H7", xyz, [1] * 7, 4, 3, [4] * 7, [0] * 7, 9,
+            net, n_walkers or 2048, 1.0, seed, "fp64|fp32-net")
     raise ValueError(f"no system workload {idx}")
 
 

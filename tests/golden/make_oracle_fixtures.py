@@ -27,7 +27,7 @@ from synth import make_config  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 # (workload, ragged batch size, number of sampled walkers from the full batch)
-PLAN = {1: (67, 16), 2: (67, 16), 3: (37, 8), 5: (5, 3)}
+PLAN = {1: (67, 16), 2: (67, 16), 3: (37, 8), 5: (5, 3), 6: (37, 8), 7: (37, 8)}
 
 
 def special_walkers(w, base):
@@ -76,7 +76,7 @@ def run(idx):
 
 
 # full adjoint (cotangents on ln|psi|, grad, lap and E_loc): workload -> walkers
-FULL_PLAN = {1: 6, 2: 5, 3: 4}
+FULL_PLAN = {1: 6, 2: 5, 3: 4, 5: 2}
 
 
 def run_full(idx):

@@ -37,7 +37,7 @@ def _run(pn, w, walkers, prec, derivs=True):
     return {k: v.cpu().numpy() for k, v in out.items()}, ctx
 
 
-@pytest.mark.parametrize("idx", [1, 2, 3, 5])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5, 6, 7])
 def test_fp64_parity_ragged_batch(pn, idx):
     try:
         fx = load_fixture(idx)
@@ -52,7 +52,7 @@ def test_fp64_parity_ragged_batch(pn, idx):
         assert v.max() <= TOL64, f"{k}: worst {v.max():.3e} at walker {int(v.argmax())}; {summarize(rat)}"
 
 
-@pytest.mark.parametrize("idx", [1, 2, 3, 5])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5, 6, 7])
 def test_fp64_parity_full_batch_sample(pn, idx):
     """Full-size batch in the benchmark's launch configuration; the oracle
     values of a sample of walkers are compared one by one.  The 30-electron
@@ -125,7 +125,7 @@ def test_mixed_precision_error_statement(pn, idx, prec, bound):
 
 
 # ------------------------------------------------------------- backward ----
-@pytest.mark.parametrize("idx", [1, 2, 3, 5])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5, 6, 7])
 def test_backward_fp64_matches_oracle(pn, idx):
     """Value-path adjoint grad += sum_w ct_w d ln|psi_w| / d theta (the
     gradient the Hermitian estimator of Methods eq. "trainig" needs) against

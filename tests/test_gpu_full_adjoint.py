@@ -44,7 +44,7 @@ def _call(pn, ctx, fx, th, which, prec, grad_params=None):
     return g
 
 
-@pytest.mark.parametrize("idx", [1, 2, 3])
+@pytest.mark.parametrize("idx", [1, 2, 3, 5])
 @pytest.mark.parametrize("which", ["grad", "lap", "eloc", "all"])
 def test_full_adjoint_fp64_matches_oracle(pn, idx, which):
     fx = _fixture(idx)
@@ -62,7 +62,7 @@ def test_full_adjoint_fp64_matches_oracle(pn, idx, which):
     assert comp <= 1e-7
 
 
-@pytest.mark.parametrize("idx,prec", [(2, "fp32"), (3, "fp32"), (3, "bf16")])
+@pytest.mark.parametrize("idx,prec", [(2, "fp32"), (3, "fp32"), (3, "bf16"), (5, "fp32")])
 def test_full_adjoint_mixed_error_statement(pn, idx, prec):
     fx = _fixture(idx)
     w = make_config(idx, n_walkers=4)

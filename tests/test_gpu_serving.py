@@ -35,7 +35,7 @@ def _state(pn, ctx, w, prec, seed, n_hist=1):
     }
 
 
-@pytest.mark.parametrize("idx", [1, 2])
+@pytest.mark.parametrize("idx", [1, 2, 6, 7])
 def test_vmc_step_matches_oracle(pn, idx):
     from oracle import Oracle
     from oracle.vmc import adamw_step, energy_gradient, metropolis_randoms, metropolis_step
@@ -72,29 +72,67 @@ def test_vmc_step_matches_oracle(pn, idx):
     assert np.max(np.abs(th_gpu - th1.numpy())) <= 2.1 * 0.01  # the rest differ at most by the sign of a ~0 step
 
 
-def test_job_same_alone_and_in_the_mix(pn):
+@pytest.mark.parametrize("grouped", [True, False])
+def test_job_same_alone_and_in_the_mix(pn, grouped):
     """Continuous batching: job A's walkers, parameters and E_loc after 4
-    steps are bit-identical whether it runs alone or interleaved with three
-    other jobs on other streams (and admitted mid-run)."""
+    steps are bit-identical whether it runs alone or together with three
+    other jobs (one admitted mid-run), in grouped steps or per-job steps."""
     from paper_1909_08423_amd.serve import GpuBackend, JobSpec, Server
     specs = []
     wa = make_config(2, n_walkers=512)
     specs.append(JobSpec(0, 0.0, 4, wa.system, wa.net, wa.params, wa.walkers, seed=5))
-    for j, (idx, B) in enumerate([(3, 768), (1, 256), (2, 1024)], start=1):
+    for j, (idx, B) in enumerate([(3, 768), (7, 256), (6, 1024)], start=1):
         wj = make_config(idx, n_walkers=B)
         specs.append(JobSpec(j, 0.0 if j < 3 else 0.02, 3, wj.system, wj.net, wj.params, wj.walkers, seed=100 + j))
-    announce("alone vs mix")
-    be = GpuBackend(prec=1, n_streams=4)
+    announce(f"alone vs mix, grouped={grouped}")
+    be = GpuBackend(prec=1, grouped=grouped)
     alone = Server(be, 1 << 36).run([specs[0]])[0]
-    be2 = GpuBackend(prec=1, n_streams=4)
+    be.close()
+    be2 = GpuBackend(prec=1, grouped=grouped)
     srv = Server(be2, 1 << 36)
     mix = srv.run(specs)
-    torch.cuda.synchronize()
+    be2.close()
     assert srv.max_concurrency >= 2
     np.testing.assert_array_equal(alone.params, mix[0].params)
     np.testing.assert_array_equal(alone.eloc, mix[0].eloc)
     np.testing.assert_array_equal(alone.stats, mix[0].stats)
     assert all(mix[j].stats is not None and np.all(mix[j].stats[:, 5] == 1.0) for j in range(4))
+
+
+def test_grouped_step_equals_per_job_steps(pn):
+    """pn_serve_step over three jobs of different systems (a 10-electron atom,
+    the odd H7 chain, H2) gives, for every job and two steps in a row, the
+    bits pn_vmc_step gives on the same state."""
+    jobs = [(2, 384, 11), (7, 256, 12), (1, 512, 13)]
+    states_g, states_1 = [], []
+    for idx, B, seed in jobs:
+        w = make_config(idx, n_walkers=B)
+        ctx = pn.PauliNetContext(w.system, w.net)
+        for lst in (states_g, states_1):
+            st = _state(pn, ctx, w, pn.PN_PREC_NET_FP32, seed)
+            st["ctx"] = ctx
+            lst.append(st)
+    announce("grouped step vs per-job steps")
+    for step in range(2):
+        pn.serve_step(states_g, pn.PN_PREC_NET_FP32)
+        for st in states_1:
+            pn.vmc_step(st["ctx"], st, pn.PN_PREC_NET_FP32)
+        torch.cuda.synchronize()
+        for a, b in zip(states_g, states_1):
+            for k in ("r", "params", "adam_m", "adam_v", "eloc", "stats"):
+                assert torch.equal(a[k], b[k]), (step, k)
+            a["step"] += 1
+            b["step"] += 1
+
+
+def test_job_bytes_cover_the_job(pn):
+    """pn_job_bytes: the resident bytes are the job's state and the scratch
+    is the step workspace."""
+    w = make_config(2, n_walkers=300)
+    ctx = pn.PauliNetContext(w.system, w.net)
+    res, scr = pn.job_bytes(ctx, 300, pn.PN_PREC_NET_FP32)
+    assert scr == pn.vmc_workspace_bytes(ctx, 300, pn.PN_PREC_NET_FP32)
+    assert res == 8 * (300 * w.system.n_elec * 3 + 3 * ctx.param_count + 300 + 8)
 
 
 def test_serving_admission_by_memory(pn):
@@ -105,7 +143,7 @@ def test_serving_admission_by_memory(pn):
     for j in range(5):
         wj = make_config(1 + (j % 2), n_walkers=256)
         specs.append(JobSpec(j, 0.0, 2, wj.system, wj.net, wj.params, wj.walkers, seed=j))
-    be = GpuBackend(prec=1, n_streams=4)
+    be = GpuBackend(prec=1)
     sizes = sorted(be.bytes(s) for s in specs)
     budget = sizes[-1] + sizes[-2]
     announce("admission by memory")
@@ -115,3 +153,4 @@ def test_serving_admission_by_memory(pn):
     assert srv.max_bytes_in_use <= budget
     order = [e[1] for e in srv.log if e[0] == "admit"]
     assert order == sorted(order)
+    be.close()

@@ -157,3 +157,49 @@ def test_result_same_alone_and_in_the_mix_cpu_oracle():
     mix = Server(OracleBackend(), 1 << 30).run([b, a])[0]
     np.testing.assert_array_equal(alone.params, mix.params)
     np.testing.assert_array_equal(alone.eloc, mix.eloc)
+
+
+class GroupedFakeBackend(TimedFakeBackend):
+    """Grouped steps: one step of every member takes `step_s` of virtual
+    time; results are collected after a copy that completes at once."""
+
+    grouped = True
+
+    def __init__(self, clock, step_s=0.01):
+        super().__init__(clock, step_s)
+        self.groups = []
+
+    def step_group(self, states):
+        self.groups.append(sorted(st["spec"].job_id for st in states))
+        for st in states:
+            st["step"] += 1
+        return self.clock.t + self.step_s
+
+    def finish_async(self, st):
+        return st
+
+    def collected(self, tok):
+        return True
+
+    def collect(self, st):
+        return self.finish(st)
+
+
+def test_grouped_steps_admit_at_step_boundaries():
+    """Grouped stepping: every admitted job finishes its steps, later
+    arrivals join the running group at a step boundary, the budget and the
+    slot limit hold, and steps that follow an admission are flagged."""
+    clk = VirtualClock()
+    be = GroupedFakeBackend(clk, step_s=0.01)
+    specs = _specs(6, [256, 512, 1024], [0.0, 0.012, 0.03], steps=8)
+    srv = Server(be, mem_budget_bytes=1024 * 1800, max_active=3, clock=clk, sleep=clk.sleep)
+    recs = srv.run(specs)
+    assert all(r.stats is not None and len(r.step_ms) == 8 for r in recs.values())
+    assert be.peak <= 1024 * 1800 and srv.max_concurrency <= 3
+    assert be.started == sorted(be.started)
+    # a group holds several jobs, and some job joins a group already running
+    assert max(len(g) for g in be.groups) >= 2
+    assert any(set(a) < set(b) for a, b in zip(be.groups, be.groups[1:]))
+    s = summarize(recs, clk.t)
+    assert s["steps"] == 48 and s["p99_step_ms_after_admission"] is not None
+    assert sum(sum(r.step_after_admission) for r in recs.values()) >= 1
