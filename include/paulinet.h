@@ -202,6 +202,23 @@ pn_status pn_eval(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers, cons
                   const double* params, pn_precision prec, double* logabs, double* sign,
                   double* grad, double* lap, double* eloc, void* ws, size_t ws_bytes);
 
+/* pn_eval without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * static device array of 128 MiB inside the library (one per GPU, held until
+ * the process ends; its address is taken when a context is created on that
+ * GPU).  Batches of any size are processed in walker tiles that fit it, so a
+ * large batch runs in more, smaller tiles than pn_eval uses; the results are
+ * those of pn_eval.  A shape whose single walker needs more than 128 MiB of
+ * workspace returns PN_ERR_WORKSPACE_TOO_SMALL; PN_ERR_DEVICE if the array's
+ * address could not be taken.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (different streams, or other host
+ * threads) race and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero. */
+pn_status pn_eval_noalloc(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers, const double* r,
+                          const double* params, pn_precision prec, double* logabs, double* sign, double* grad,
+                          double* lap, double* eloc);
+
 /* Parameter adjoint of the evaluation:
  *   grad_params[t] += sum_w ( ct_logabs[w] d ln|psi_w| / d theta_t
  *                           + sum_a ct_grad[w][a] d (d_a ln|psi_w|) / d theta_t

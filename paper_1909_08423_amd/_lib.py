@@ -155,6 +155,8 @@ def load_library():
     lib.pn_vmc_step.argtypes = [vp, vp, ctypes.POINTER(pn_vmc_job), i32, ctypes.POINTER(pn_vmc_hparams), vp,
                                 ctypes.c_size_t]
     lib.pn_vmc_step.restype = i32
+    lib.pn_eval_noalloc.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.pn_eval_noalloc.restype = i32
     lib.pn_job_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.pn_job_bytes.restype = i32
     lib.pn_serve_step.argtypes = [vp, ctypes.POINTER(pn_job_slot), i32, i32, ctypes.POINTER(pn_vmc_hparams)]
@@ -318,6 +320,22 @@ class PauliNetContext:
                                _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out.get("grad")),
                                _ptr(out.get("lap")), _ptr(out.get("eloc")), _ptr(ws), ws.numel())
         _check(st, "pn_eval")
+        return out
+
+    def eval_noalloc(self, r, params, prec=PN_PREC_FP64, out=None):
+        """pn_eval_noalloc: as eval, with the library's static workspace."""
+        import torch
+        r = r.contiguous()
+        params = params.contiguous()
+        B = int(r.shape[0])
+        if out is None:
+            dev = r.device
+            out = {k: torch.empty(B, dtype=torch.float64, device=dev) for k in ("logabs", "sign", "lap", "eloc")}
+            out["grad"] = torch.empty(B, self.n_elec, 3, dtype=torch.float64, device=dev)
+        st = self._lib.pn_eval_noalloc(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
+                                       _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out.get("grad")),
+                                       _ptr(out.get("lap")), _ptr(out.get("eloc")))
+        _check(st, "pn_eval_noalloc")
         return out
 
     def eval_backward(self, r, params, ct_logabs=None, prec=PN_PREC_FP64, grad_params=None, ws=None,

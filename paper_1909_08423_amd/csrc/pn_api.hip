@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "pn_internal.h"
@@ -158,7 +159,10 @@ void plan_full_adjoint(const Dims& d, bool fp64, WsLayout& L) {
   L.tadj_arena = fp64 ? tangent_adj_arena_elems<double>(d, L.T) : tangent_adj_arena_elems<float>(d, L.T);
 }
 
-WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
+// `budget`: workspace bytes the walker tile is sized for; min_tile: the
+// smallest tile (the library's own budget keeps tiles of >= 256 walkers).
+WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t budget_bytes = kWsBudget,
+              int64_t min_tile = 256) {
   const Dims& d = c->d;
   const bool fp64 = prec == PN_PREC_FP64;
   const bool backward = mode >= kPlanValueAdjoint, full = mode == kPlanFullAdjoint;
@@ -258,7 +262,11 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode) {
     return b;
   };
   size_t pw = per_walker(backward);
-  int64_t tile = (int64_t)std::max<size_t>(256, kWsBudget / std::max<size_t>(pw, 1));
+  // bytes that do not scale with the tile: the converted parameters and the
+  // alignment of every region
+  const size_t fixed = (fp64 ? 0 : align_up((size_t)c->pl.total * sizeof(float))) + 64 * kAlign;
+  const size_t avail = budget_bytes > fixed ? budget_bytes - fixed : 0;
+  int64_t tile = std::max<int64_t>(min_tile, (int64_t)(avail / std::max<size_t>(pw, 1)));
   tile = std::min<int64_t>(tile, std::max<int64_t>(nw, 1));
   L.tile = tile;
   size_t off = 0;
@@ -358,9 +366,43 @@ struct StageClock {
 };
 }  // namespace
 
+// ---- allocation-free evaluation (pn_eval_noalloc) ----
+// A file-scope device array serves as the workspace of pn_eval_noalloc.
+// Host code never passes the array's name to a kernel: each device's copy
+// has its own address, taken once per device by hipGetSymbolAddress at
+// context creation (with that device current) and kept in scratch_ptr.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[dev]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) scratch_ptr[dev] = p;
+  else (void)hipGetLastError();
+}
+
+void* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_ptr[dev];
+}
+}  // namespace
+
 }  // namespace pn
 
 using namespace pn;
+
+namespace {
+pn_status eval_impl(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                    pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc, char* base,
+                    const WsLayout& L);
+}
 
 extern "C" {
 
@@ -440,6 +482,7 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
   d.v_nn = vnn;
   c->pl = make_layout(d);
   if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  scratch_setup(c->device);
 
   // ---- host tables ----
   std::vector<double> nuc(sys->nuc_xyz, sys->nuc_xyz + 3 * NN), chg(sys->charge, sys->charge + NN);
@@ -773,11 +816,33 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
   if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
   if (nw == 0) return PN_OK;
   if (!r || !params || !logabs || !sign || !ws) return PN_ERR_INVALID_ARG;
-  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
   WsLayout L = plan(c, nw, prec, kPlanForward);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
   if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
-  char* base = static_cast<char*>(ws);
+  return eval_impl(c, s, nw, r, params, prec, logabs, sign, grad, lap, eloc, static_cast<char*>(ws), L);
+}
+
+pn_status pn_eval_noalloc(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                          pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc) {
+  if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
+  if (nw == 0) return PN_OK;
+  if (!r || !params || !logabs || !sign) return PN_ERR_INVALID_ARG;
+  char* base = static_cast<char*>(scratch_of(c->device));
+  if (!base) return PN_ERR_DEVICE;
+  // walker tiles sized for the static scratch (down to one walker)
+  WsLayout L = plan(c, nw, prec, kPlanForward, kScratchBytes, 1);
+  if (L.total > kScratchBytes) return PN_ERR_WORKSPACE_TOO_SMALL;
+  if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
+  return eval_impl(c, s, nw, r, params, prec, logabs, sign, grad, lap, eloc, base, L);
+}
+
+}  // extern "C"
+
+namespace {
+pn_status eval_impl(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
+                    pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc, char* base,
+                    const WsLayout& L) {
+  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
   const bool derivs = grad || lap || eloc;
   const Dims& d = c->d;
   const bool no_net = (d.flags & (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW)) == (PN_NET_NO_JASTROW | PN_NET_NO_BACKFLOW);
@@ -847,6 +912,9 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
   if (hipGetLastError() != hipSuccess) return PN_ERR_DEVICE;
   return PN_OK;
 }
+}  // namespace
+
+extern "C" {
 
 pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
                            pn_precision prec, const double* ct_logabs, const double* ct_grad, const double* ct_lap,
