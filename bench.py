@@ -394,6 +394,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other workloads")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the headline, the FP64 path and the stage pass only (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -491,6 +493,9 @@ def main():
     if probe is not None:
         res["copy_probe"] = probe
     print(json.dumps({"progress": "headline done", "value": value}), file=sys.stderr, flush=True)
+    if args.only_headline:
+        print(json.dumps(res), flush=True)
+        return
     res["vmc_step"] = time_vmc_step(pn, ctx, w, pmix, 3, 1, torch)
     if not args.no_backward:
         res["value_adjoint"] = {args.prec: time_backward(ctx, r, th, pmix, 3, 1, torch, False)}

@@ -60,9 +60,11 @@ __device__ __forceinline__ void dma16(uint4* __restrict__ dst, const uint4* __re
 
 // BF16 is a template parameter so that the FP32 and FP64 instantiations
 // carry no BF16 operand code (smaller kernels, fewer instruction-cache
-// misses).
-template <typename TN, int C, bool STAGE, bool BF16>
-__global__ __launch_bounds__(kThreadsT, 2) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
+// misses).  NT threads per block: 256 with two blocks per CU (80 KB of LDS
+// each), or 512 with one block per CU when a block takes all 160 KB (two
+// waves per SIMD either way, so the register budget is the same).
+template <typename TN, int C, bool STAGE, bool BF16, int NT>
+__global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables t, int64_t nw, int n_chunks,
                                                            const double* __restrict__ r, const TN* __restrict__ P,
                                                            ParamLayout pl, const TN* __restrict__ filt,
                                                            const TN* __restrict__ hval, const TN* __restrict__ kcoef,
@@ -516,22 +518,38 @@ template <typename TN, int C, bool STAGE>
 void launch_c(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const TN* P, char* ws, const WsLayout& L,
               bool bf16, TN* xsave) {
   const int64_t nb = nw * L.n_chunks;
+  int nt = kThreadsT;
   auto go = [&](auto kern) {
     if (L.lds_tangent > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)L.lds_tangent);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kThreadsT), L.lds_tangent, s, c->d, c->t, nw, L.n_chunks, r, P,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(nt), L.lds_tangent, s, c->d, c->t, nw, L.n_chunks, r, P,
                        c->pl, reinterpret_cast<const TN*>(ws + L.filt), reinterpret_cast<const TN*>(ws + L.hval),
                        reinterpret_cast<const TN*>(ws + L.kcoef), reinterpret_cast<const TN*>(ws + L.ecoef),
                        reinterpret_cast<double*>(ws + L.ftan), reinterpret_cast<double*>(ws + L.jtan), xsave, bf16);
   };
-  if constexpr (sizeof(TN) == sizeof(float)) {
-    if (bf16) {
-      go(&k_net_tangent<TN, C, STAGE, true>);
+  // one 512-thread block per CU where the planner gives a block all the LDS
+  // (instantiated for the chunk sizes that rule produces)
+  if constexpr (C <= 7) {
+    if (L.tan_threads == 512) {
+      nt = 512;
+      if constexpr (sizeof(TN) == sizeof(float)) {
+        if (bf16) {
+          go(&k_net_tangent<TN, C, STAGE, true, 512>);
+          return;
+        }
+      }
+      go(&k_net_tangent<TN, C, STAGE, false, 512>);
       return;
     }
   }
-  go(&k_net_tangent<TN, C, STAGE, false>);
+  if constexpr (sizeof(TN) == sizeof(float)) {
+    if (bf16) {
+      go(&k_net_tangent<TN, C, STAGE, true, kThreadsT>);
+      return;
+    }
+  }
+  go(&k_net_tangent<TN, C, STAGE, false, kThreadsT>);
 }
 
 template <typename TN, bool STAGE>

@@ -215,6 +215,9 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
   }
   L.n_chunks = (ncoord + L.T - 1) / L.T;
   L.lds_tangent = lds_of(L.T, L.stage_filters);
+  // a block that takes more than half the CU's LDS runs alone on it: 512
+  // threads keep two waves per SIMD (chunks of at most 6 coordinates)
+  L.tan_threads = (L.lds_tangent > kLdsMax / 2 && L.T <= 6) ? 512 : 256;
   L.wpb_value = std::max(1, 64 / d.N);
   while (L.wpb_value > 1 &&
          (fp64 ? value_lds_bytes<double>(d, L.wpb_value) : value_lds_bytes<float>(d, L.wpb_value)) > 64 * 1024)

@@ -95,6 +95,7 @@ struct WsLayout {
   int n_chunks;
   int wpb_value;       // walkers per block in the value network kernel
   size_t lds_tangent;  // dynamic LDS of the tangent kernel
+  int tan_threads;     // threads per tangent block: 256 (two blocks per CU) or 512 (one block, all LDS)
   size_t lds_value;
   size_t lds_filter;
   int filt_rows;       // pairs per block in the filter kernel
