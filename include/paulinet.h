@@ -63,11 +63,17 @@ typedef enum {
 
 /* Arithmetic of the network (distance features, filters, interaction
  * layers, Jastrow and backflow heads).  Geometry, orbitals, determinants,
- * their derivatives and E_loc are always FP64. */
+ * their derivatives and E_loc are always FP64.  In the BF16 form only the
+ * dense products of the derivative (tangent) pass take BF16 operands; the
+ * value pass (filters, layers and heads on the values) stays FP32, because
+ * BF16 values of the backflow, the Jastrow factor and the stored filter
+ * values move E_loc by orders of magnitude more than FP32 rounding does,
+ * while BF16 tangent products leave the batch-mean E_loc at the FP32 level. */
 typedef enum {
   PN_PREC_FP64 = 0,     /* network in FP64                                  */
   PN_PREC_NET_FP32 = 1, /* network in FP32                                  */
-  PN_PREC_NET_BF16 = 2  /* network dense layers: BF16 operands, FP32 accum.  */
+  PN_PREC_NET_BF16 = 2  /* FP32 value pass; tangent products BF16 operands,
+                           FP32 accumulation                                */
 } pn_precision;
 
 typedef struct pn_ctx pn_ctx; /* opaque; immutable after create */
@@ -235,9 +241,10 @@ pn_status pn_eval_noalloc(const pn_ctx* ctx, hipStream_t stream, int64_t n_walke
  * ACCUMULATED into.  The forward values are recomputed inside the call
  * (nothing is stored between calls).  Per-walker contributions are reduced
  * in a fixed order, so the result does not depend on what else runs on the
- * device.  In the BF16 mode the forward recomputation uses BF16 operands and
- * the adjoint products FP32.  Shapes whose adjoint blocks exceed the LDS
- * limit return PN_ERR_UNSUPPORTED_SHAPE. */
+ * device.  In the BF16 mode the recomputed value pass is FP32 and the
+ * recomputed tangent pass (full adjoint) takes BF16 operands; the adjoint
+ * products are FP32.  Shapes whose adjoint blocks exceed the LDS limit
+ * return PN_ERR_UNSUPPORTED_SHAPE. */
 pn_status pn_eval_backward(const pn_ctx* ctx, hipStream_t stream, int64_t n_walkers,
                            const double* r, const double* params, pn_precision prec,
                            const double* ct_logabs, const double* ct_grad, const double* ct_lap,

@@ -845,6 +845,9 @@ namespace {
 pn_status eval_impl(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, const double* params,
                     pn_precision prec, double* logabs, double* sign, double* grad, double* lap, double* eloc, char* base,
                     const WsLayout& L) {
+  // PN_PREC_NET_BF16: BF16 operands in the tangent (derivative) products
+  // only; the value pass stays FP32 (BF16 values of f, J and of the stored
+  // filter values and slopes move E_loc by far more than FP32 does)
   const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
   const bool derivs = grad || lap || eloc;
   const Dims& d = c->d;
@@ -876,10 +879,10 @@ pn_status eval_impl(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r,
       clk.end(3);
     } else {
       clk.begin(2);
-      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, false);
       clk.end(2);
       clk.begin(3);
-      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, false);
       clk.end(3);
     }
     clk.begin(4);
@@ -955,8 +958,8 @@ pn_status pn_eval_backward(const pn_ctx* c, hipStream_t s, int64_t nw, const dou
       launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
       launch_net_value<double>(c, s, n, static_cast<const double*>(P), base, L, false);
     } else {
-      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
-      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, false);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, false);
     }
     launch_slater_value(c, s, n, base, L, la, sg);
     const double* ctl = ct_logabs ? ct_logabs + w0 : nullptr;
@@ -1021,8 +1024,8 @@ pn_status pn_eval_backward_cusp(const pn_ctx* c, hipStream_t s, int64_t nw, cons
       launch_filters<double>(c, s, n, rt, static_cast<const double*>(P), base, L, false);
       launch_net_value<double>(c, s, n, static_cast<const double*>(P), base, L, false);
     } else {
-      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, bf16);
-      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, bf16);
+      launch_filters<float>(c, s, n, rt, static_cast<const float*>(P), base, L, false);
+      launch_net_value<float>(c, s, n, static_cast<const float*>(P), base, L, false);
     }
     launch_slater_value(c, s, n, base, L, la, sg);
     launch_cusp_grad(c, s, n, rt, base, L, ct_logabs + w0, slot, grad_cusp);

@@ -107,12 +107,18 @@ def test_antisymmetry_on_gpu(pn):
     np.testing.assert_allclose(b["eloc"], a["eloc"], rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 1e-3), (3, "fp32", 1e-3), (5, "fp32", 1e-3), (2, "bf16", 0.2), (3, "bf16", 0.2)])
+# p99 ratios measured on the fixture batches (ln|psi|, E_loc), about 3x
+# as the gate: FP32 cfg2 1.4e-6 / 2.1e-7, cfg3 1.0e-7 / 6.3e-8, cfg5 4.3e-6 /
+# 2.9e-6; BF16 tangent products cfg2 1.4e-6 / 6.6e-6, cfg3 1.0e-7 / 4.2e-6,
+# cfg5 4.3e-6 / 3.5e-4.
+@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 5e-6), (3, "fp32", 3e-7), (5, "fp32", 1.5e-5),
+                                            (2, "bf16", 2e-5), (3, "bf16", 1.5e-5), (5, "bf16", 1.1e-3)])
 def test_mixed_precision_error_statement(pn, idx, prec, bound):
-    """Mixed modes: the network in FP32 (or BF16 operands with FP32
-    accumulation), determinants and E_loc in FP64.  The per-output error
-    against the FP64 oracle is printed; the bound only guards against
-    gross breakage."""
+    """Mixed modes: the network in FP32 (or, in the tangent products, BF16
+    operands with FP32 accumulation), determinants and E_loc in FP64.  The
+    per-output error against the FP64 oracle is printed; the p99 of the
+    ln|psi| and E_loc ratios must stay within about three times what was
+    measured."""
     fx = load_fixture(idx)
     w = make_config(idx, n_walkers=4)
     announce(f"{prec} error statement workload {idx}")
@@ -163,7 +169,7 @@ def test_backward_mixed_error_statement(pn, idx, prec):
     got, ref = g.cpu().numpy(), fx["bwd_grad"]
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"[{prec} backward cfg{idx}] relative L2 error {rel:.3e}")
-    assert rel < (1e-3 if prec == "fp32" else 0.2)
+    assert rel < (3e-4 if idx == 2 else 1e-6)  # measured 8.5e-5 (cfg2), 2.9e-7 (cfg3, FP32 and BF16)
 
 
 def test_backward_deterministic_and_batch_split(pn):
