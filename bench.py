@@ -111,7 +111,7 @@ def tangent_source_digest():
     return h.hexdigest()
 
 
-def stored_traffic(prec, T, tile):
+def stored_traffic(prec, T, tile, walkers):
     """HBM bytes per launch of the tangent kernel from the committed counter
     summary, or None when that summary was taken on other kernel sources or
     another launch configuration."""
@@ -124,7 +124,8 @@ def stored_traffic(prec, T, tile):
         if line.startswith("traffic-record: "):
             rec = json.loads(line[len("traffic-record: "):])
             if (rec.get("sha256") == tangent_source_digest() and rec.get("prec") == prec
-                    and rec.get("chunk_coords") == T and rec.get("walkers_per_launch") == tile):
+                    and rec.get("chunk_coords") == T and rec.get("tile_walkers") == tile
+                    and rec.get("walkers") == walkers):
                 return rec["hbm_bytes_per_launch"]
     return None
 
@@ -178,12 +179,27 @@ def stage_pass(ctx, r, th, prec, steps, torch):
     return st
 
 
+def clipped_mean(e, q=5.0):
+    """Batch mean of E_loc clipped as the VMC update clips it (Methods,
+    "Ansatz optimization"): logarithmic growth outside q mean absolute
+    deviations from the median."""
+    e = np.asarray(e, dtype=np.float64)
+    m = np.median(e)
+    w = q * np.mean(np.abs(e - m))
+    dev = np.abs(e - m)
+    if w == 0:
+        return float(e.mean())
+    ec = np.where(dev <= w, e, m + np.sign(e - m) * w * (1.0 + np.log(np.maximum(dev, w) / w)))
+    return float(ec.mean())
+
+
 def error_stats(e_mix, e_64):
     de = np.abs(e_mix - e_64)
     B = e_64.shape[0]
     return {
         "mean_eloc_fp64": float(e_64.mean()),
         "abs_dmean_eloc_Ha": float(abs(e_mix.mean() - e_64.mean())),
+        "abs_dclipped_mean_Ha": float(abs(clipped_mean(e_mix) - clipped_mean(e_64))),
         "stderr_eloc_Ha": float(e_64.std() / math.sqrt(B)),
         "p50_abs_deloc_Ha": float(np.percentile(de, 50)),
         "p99_abs_deloc_Ha": float(np.percentile(de, 99)),
@@ -234,6 +250,8 @@ def other_workloads(pn, torch, steps=3, warmup=1):
                 ent["eloc_error_vs_fp64"] = error_stats(o["eloc"], o64["eloc"])
                 ent["output_ratios_p50_p99_max"] = output_error_stats(o, o64)
             rec[prec] = ent
+        if "bf16" in rec and "fp32" in rec:
+            rec["bf16"]["speedup_over_fp32"] = rec["bf16"]["walker_evals_per_s"] / rec["fp32"]["walker_evals_per_s"]
         ctx.close()
         out[w.name] = rec
     return out
@@ -353,6 +371,32 @@ def time_langevin(pn, ctx, w, prec, steps, torch):
             "last_acceptance": float(st[-1, 0]), "last_tau": float(st[-1, 1])}
 
 
+def time_line_scan(pn, torch, idx=3, n_points=1001, reps=20):
+    """Latency of a one-dimensional scan (electron 0 moved along the
+    molecular axis with the other electrons fixed, every output at every
+    point, FP64): median over `reps` scans, walker batch built on the device."""
+    from paper_1909_08423_amd.scan import line_scan
+    from synth import make_config
+    w = make_config(idx, n_walkers=4)
+    ctx = pn.PauliNetContext(w.system, w.net)
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    z = w.system.nuc_xyz[:, 2]
+    a, b = [0.013, -0.011, float(z.min()) - 2.0], [0.013, -0.011, float(z.max()) + 2.0]
+    ws = ctx.workspace(n_points, pn.PN_PREC_FP64, torch.device("cuda"))
+    line_scan(ctx, th, w.walkers[0], 0, a, b, n_points, ws=ws)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        line_scan(ctx, th, w.walkers[0], 0, a, b, n_points, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ctx.close()
+    return {"workload": w.name, "points": n_points, "median_ms_per_scan": float(np.median(ms)),
+            "p99_ms_per_scan": float(np.percentile(ms, 99)), "reps": reps}
+
+
 def run_serving(pn, prec, n_jobs, n_steps, torch, mean_gap_s=0.25, budget_gib=64):
     """The serving stream (H-chains and atoms, 2-18 electrons, 1-32
     determinants, 1024-8192 walkers, Poisson arrivals): n_jobs jobs of
@@ -382,6 +426,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=5, help="timed calls of the FP64 comparison path")
+    ap.add_argument("--bf16-steps", type=int, default=5, help="timed calls of the BF16 form (0: skip)")
     ap.add_argument("--stage-steps", type=int, default=3, help="calls of the per-stage timing pass")
     ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp64"])
@@ -429,6 +474,16 @@ def main():
     o_64 = {k: v.double().cpu().numpy().copy() for k, v in out_64.items()}
     value = B * args.steps / dt_mix
     plan_mix, plan_64 = ctx.plan(B, pmix), ctx.plan(B, p64)
+    # the BF16 form (BF16 operands in the tangent products) on the same batch
+    alt = None
+    if args.prec == "fp32" and args.bf16_steps > 0:
+        dt_b, ms_b, out_b = time_path(ctx, r, th, P["bf16"], args.bf16_steps, 1, torch)
+        o_b = {k: v.double().cpu().numpy().copy() for k, v in out_b.items()}
+        alt = {"value": B * args.bf16_steps / dt_b, "median_ms_per_step": float(np.median(ms_b)),
+               "speedup_over_fp32": (B * args.bf16_steps / dt_b) / value,
+               "eloc_error_vs_fp64": error_stats(o_b["eloc"], o_64["eloc"]),
+               "output_ratios_vs_fp64_p50_p99_max": output_error_stats(o_b, o_64)}
+        del out_b
 
     # ---- per-stage times (separate pass) and rooflines ----
     st_mix = stage_pass(ctx, r, th, pmix, args.stage_steps, torch)
@@ -444,7 +499,7 @@ def main():
     ach = tan_fl * walkers_per_launch / (tan_ms_launch * 1e-3) / 1e12
     roof = {"kernel": "k_net_tangent", "bound": "mfma", "achieved": ach, "peak": peak_net, "unit": "TFLOP/s",
             "frac": ach / peak_net,
-            "traffic": stored_traffic(args.prec, plan_mix["chunk_coords"], plan_mix["tile_walkers"]),
+            "traffic": stored_traffic(args.prec, plan_mix["chunk_coords"], plan_mix["tile_walkers"], B),
             "flops_per_walker": tan_fl, "jet_columns": 3 * s.n_elec + 1, "walkers_per_launch": walkers_per_launch,
             "avg_launch_ms": tan_ms_launch, "launches_per_step": tan_launches,
             "chunk_coords": plan_mix["chunk_coords"]}
@@ -484,6 +539,7 @@ def main():
         "speedup_vs_fp64": (B * args.steps / dt_mix) / (B * args.fp64_steps / dt_64),
         "eloc_error_vs_fp64": error_stats(o_mix["eloc"], o_64["eloc"]),
         "output_ratios_vs_fp64_p50_p99_max": output_error_stats(o_mix, o_64),
+        "bf16_form": alt,
         "stages_ms_per_step": stages_mix,
         "stages_ms_per_step_fp64": stages_64,
         "roofline": roof,
@@ -506,6 +562,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_other:
         res["other_workloads"] = other_workloads(pn, torch)
+        res["line_scan"] = time_line_scan(pn, torch)
     print(json.dumps({"progress": "side measurements done"}), file=sys.stderr, flush=True)
     if not args.no_serve:
         res["serving"] = run_serving(pn, pmix, args.serve_jobs, args.serve_steps, torch, args.serve_gap,
