@@ -145,7 +145,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
     const int rw = (rt << 4) + c16 - lo;
     const bool inw = !WIN || (rw >= 0 && rw < n);
     const int r = WIN ? (inw ? rw : 0) : min((rt << 4) + c16, rows - 1);
-    const TN* xr = X + (size_t)r * ldx + g * KQ;
+    const TN* xr = X + r * ldx + g * KQ;
     if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
       constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
       const uint4* xv = reinterpret_cast<const uint4*>(xr);
@@ -167,7 +167,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
   auto load_a2 = [&](int rt, TN* af) {
     const int rw = (rt << 4) + c16 - lo;
     const bool inw = rw >= 0 && rw < n;
-    const TN* xr = X2 + (size_t)(inw ? rw : 0) * ldx2 + g * KQ;
+    const TN* xr = X2 + (inw ? rw : 0) * ldx2 + g * KQ;
     if constexpr ((KQ * sizeof(TN)) % 16 == 0) {
       constexpr int NV = (int)(KQ * sizeof(TN) / 16), PV = (int)(16 / sizeof(TN));
       const uint4* xv = reinterpret_cast<const uint4*>(xr);
@@ -191,11 +191,11 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
     TN bfrag[KQ];
 #pragma unroll
     for (int s = 0; s < KQ; ++s)
-      bfrag[s] = colok ? (WT ? W[(size_t)col * ldw + g * KQ + s] : W[(size_t)(g * KQ + s) * ldw + col]) : TN(0);
+      bfrag[s] = colok ? (WT ? W[col * ldw + g * KQ + s] : W[(g * KQ + s) * ldw + col]) : TN(0);
     TN bfrag2[DUAL ? KQ : 1];
     if constexpr (DUAL) {
 #pragma unroll
-      for (int s = 0; s < KQ; ++s) bfrag2[s] = colok ? W2[(size_t)(g * KQ + s) * ldw + col] : TN(0);
+      for (int s = 0; s < KQ; ++s) bfrag2[s] = colok ? W2[(g * KQ + s) * ldw + col] : TN(0);
     }
     auto second = [&](int rt, acc_t c) -> acc_t {
       if constexpr (DUAL) {
@@ -221,8 +221,8 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = MfmaTile<TN>::row_of(lane, v);
-          ca[v] = accumulate ? Y[(size_t)((rt << 4) + row) * ldy + col] : TN(0);
-          cb[v] = accumulate ? Y[(size_t)((rtb << 4) + row) * ldy + col] : TN(0);
+          ca[v] = accumulate ? Y[((rt << 4) + row) * ldy + col] : TN(0);
+          cb[v] = accumulate ? Y[((rtb << 4) + row) * ldy + col] : TN(0);
         }
         ca = MfmaChain<TN, KQ>::run(afa, bfrag, ca, bf16);
         cb = MfmaChain<TN, KQ>::run(afb, bfrag, cb, bf16);
@@ -231,8 +231,8 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = MfmaTile<TN>::row_of(lane, v);
-          Y[(size_t)((rt << 4) + row) * ldy + col] = ca[v];
-          Y[(size_t)((rtb << 4) + row) * ldy + col] = cb[v];
+          Y[((rt << 4) + row) * ldy + col] = ca[v];
+          Y[((rtb << 4) + row) * ldy + col] = cb[v];
         }
       }
     }
@@ -245,28 +245,28 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-          c[v] = accumulate ? Y[(size_t)row * ldy + col] : TN(0);
+          c[v] = accumulate ? Y[row * ldy + col] : TN(0);
         }
         c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
         c = second(rt, c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-          Y[(size_t)row * ldy + col] = c[v];
+          Y[row * ldy + col] = c[v];
         }
         continue;
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-        c[v] = (accumulate && row < rows && colok) ? Y[(size_t)row * ldy + col] : TN(0);
+        c[v] = (accumulate && row < rows && colok) ? Y[row * ldy + col] : TN(0);
       }
       c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
       c = second(rt, c);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
-        if (row < rows && colok) Y[(size_t)row * ldy + col] = c[v];
+        if (row < rows && colok) Y[row * ldy + col] = c[v];
       }
     }
   }

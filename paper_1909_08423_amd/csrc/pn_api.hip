@@ -14,7 +14,7 @@
 namespace pn {
 
 template <typename TN>
-size_t tangent_lds_bytes(const Dims& d, int T, bool stage);
+size_t tangent_lds_bytes(const Dims& d, int T, int stage);
 template <typename TN>
 size_t value_lds_bytes(const Dims& d, int wpb);
 size_t slater_tangent_lds_bytes(const Dims& d, int T);
@@ -136,7 +136,7 @@ enum { kPlanForward = 0, kPlanValueAdjoint = 1, kPlanFullAdjoint = 2 };
 // forward tangent pass runs with the same chunks, so its block must fit too.
 void plan_full_adjoint(const Dims& d, bool fp64, WsLayout& L) {
   auto lds = [&](int T, bool ga) {
-    const size_t fwd = fp64 ? tangent_lds_bytes<double>(d, T, false) : tangent_lds_bytes<float>(d, T, false);
+    const size_t fwd = fp64 ? tangent_lds_bytes<double>(d, T, 0) : tangent_lds_bytes<float>(d, T, 0);
     if (fwd > kLdsMax) return fwd;
     return fp64 ? tangent_adj_lds_bytes<double>(d, T, ga) : tangent_adj_lds_bytes<float>(d, T, ga);
   };
@@ -178,7 +178,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
   // per-chunk work of the heads would be repeated 3N times): then one block
   // per CU with all 160 KB, if that at least doubles the chunk.
   const int ncoord = 3 * d.N;
-  auto lds_of = [&](int T, bool stage) {
+  auto lds_of = [&](int T, int stage) {
     return fp64 ? tangent_lds_bytes<double>(d, T, stage) : tangent_lds_bytes<float>(d, T, stage);
   };
   auto pick = [&](size_t budget, int& T_out, bool& stage_out) {
@@ -188,7 +188,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
       if (!tangent_chunk_supported(T)) continue;
       for (int pass = 0; pass < 2; ++pass) {
         const bool stage = pass == 0;
-        if (lds_of(T, stage) <= budget || (!stage && T == 1)) {
+        if (lds_of(T, stage ? 2 : 0) <= budget || (!stage && T == 1)) {
           T_out = T;
           stage_out = stage;
           break;
@@ -211,10 +211,10 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
   if (full) {
     // the forward tangent pass runs with the adjoint's chunking
     plan_full_adjoint(d, fp64, L);
-    L.stage_filters = lds_of(L.T, true) <= budget;
+    L.stage_filters = lds_of(L.T, 2) <= budget;
   }
   L.n_chunks = (ncoord + L.T - 1) / L.T;
-  L.lds_tangent = lds_of(L.T, L.stage_filters);
+  L.lds_tangent = lds_of(L.T, L.stage_filters ? 2 : 0);
   // a block that takes more than half the CU's LDS runs alone on it: 512
   // threads keep two waves per SIMD (chunks of at most 6 coordinates)
   L.tan_threads = (L.lds_tangent > kLdsMax / 2 && L.T <= 6) ? 512 : 256;
@@ -607,6 +607,12 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
         pij.push_back(j);
         pidx[(size_t)i * N + j] = p;
         pidx[(size_t)j * N + i] = p;
+      }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (i != j && pair_of(i, j, N, d.n_up) != pidx[(size_t)i * N + j]) {
+        delete c;
+        return PN_ERR_UNSUPPORTED_SHAPE;
       }
 
   // the expansion as excitations of its first determinant (low-rank path):
