@@ -167,10 +167,28 @@ typedef struct {
  * too small, so a call with cap = 0 queries the count. */
 pn_status pn_param_layout(const pn_ctx* ctx, pn_param_entry* entries, int32_t cap, int32_t* n);
 
-/* Workspace bytes for a call with n_walkers walkers at the given
- * precision.  Batches larger than the internal walker tile are processed
- * tile by tile, so the size stops growing at the tile. */
-pn_status pn_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, size_t* bytes);
+/* Outputs a pn_eval call produces (out_mask of pn_workspace_bytes): a call
+ * whose grad, lap and eloc are all NULL runs the value pass only and needs
+ * no tangent buffers. */
+#define PN_OUT_LOGABS 1u  /* logabs and sign (always produced) */
+#define PN_OUT_GRAD 2u
+#define PN_OUT_LAP 4u
+#define PN_OUT_ELOC 8u
+#define PN_OUT_ADJOINT 16u /* also pn_eval_backward with only ct_logabs */
+#define PN_OUT_ALL 31u
+
+/* Workspace bytes for the calls out_mask names, with n_walkers walkers at
+ * the given precision: pn_eval calls whose non-NULL outputs are among its
+ * PN_OUT_LOGABS / GRAD / LAP / ELOC bits (LOGABS alone: value-only calls,
+ * which need no tangent buffers; any of GRAD, LAP, ELOC: the full forward
+ * pass), and with PN_OUT_ADJOINT pn_eval_backward with only ct_logabs (the
+ * value-path adjoint, whose per-block gradient slots can dominate small
+ * batches).  Batches larger than the internal walker tile are processed tile
+ * by tile, so the size stops growing at the tile.  PN_ERR_INVALID_ARG for
+ * bits outside PN_OUT_ALL; a call that needs more than the workspace it is
+ * given returns PN_ERR_WORKSPACE_TOO_SMALL. */
+pn_status pn_workspace_bytes(const pn_ctx* ctx, int64_t n_walkers, pn_precision prec, uint32_t out_mask,
+                             size_t* bytes);
 
 /* Workspace bytes that also cover pn_eval_backward with cotangents on the
  * gradient, Laplacian or local energy (the full adjoint keeps the layer
@@ -181,9 +199,10 @@ pn_status pn_workspace_bytes_full(const pn_ctx* ctx, int64_t n_walkers, pn_preci
 /* How a call with n_walkers walkers is carried out: walkers per internal
  * tile, coordinates per chunk of the tangent (derivative) pass, number of
  * chunks, whether the determinants take the low-rank path (PN_DET_DIRECT),
- * and the workspace bytes of that call.  kind: 0 = pn_eval, 1 =
- * pn_eval_backward with only ct_logabs (value-path adjoint), 2 =
- * pn_eval_backward with coordinate cotangents (full adjoint).  [host] out. */
+ * and the workspace bytes of that call.  kind: 0 = pn_eval with derivative
+ * outputs, 1 = pn_eval_backward with only ct_logabs (value-path adjoint),
+ * 2 = pn_eval_backward with coordinate cotangents (full adjoint), 3 =
+ * pn_eval without derivative outputs (value pass only).  [host] out. */
 typedef struct {
   int64_t tile_walkers;
   int32_t chunk_coords;

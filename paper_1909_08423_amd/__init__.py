@@ -7,6 +7,16 @@ library and a ROCm device and raises if either is missing.
 """
 
 from ._lib import (  # noqa: F401
+    PLAN_EVAL,
+    PLAN_FULL_ADJOINT,
+    PLAN_VALUE_ADJOINT,
+    PLAN_VALUE_ONLY,
+    PN_OUT_ADJOINT,
+    PN_OUT_ALL,
+    PN_OUT_ELOC,
+    PN_OUT_GRAD,
+    PN_OUT_LAP,
+    PN_OUT_LOGABS,
     PN_PREC_FP64,
     PN_PREC_NET_BF16,
     PN_PREC_NET_FP32,

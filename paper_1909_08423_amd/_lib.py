@@ -62,7 +62,9 @@ class pn_plan_info(ctypes.Structure):
 
 
 PN_DET_DIRECT = 4
-PLAN_EVAL, PLAN_VALUE_ADJOINT, PLAN_FULL_ADJOINT = 0, 1, 2
+PN_OUT_LOGABS, PN_OUT_GRAD, PN_OUT_LAP, PN_OUT_ELOC, PN_OUT_ADJOINT = 1, 2, 4, 8, 16
+PN_OUT_ALL = 31
+PLAN_EVAL, PLAN_VALUE_ADJOINT, PLAN_FULL_ADJOINT, PLAN_VALUE_ONLY = 0, 1, 2, 3
 
 
 class pn_param_entry(ctypes.Structure):
@@ -129,7 +131,7 @@ def load_library():
     lib.pn_ctx_destroy.restype = None
     lib.pn_param_count.argtypes = [vp]
     lib.pn_param_count.restype = i64
-    lib.pn_workspace_bytes.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pn_workspace_bytes.argtypes = [vp, i64, i32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pn_workspace_bytes.restype = i32
     lib.pn_eval.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.pn_eval.restype = i32
@@ -269,16 +271,21 @@ class PauliNetContext:
                 "n_chunks": int(info.n_chunks), "lowrank": bool(info.lowrank),
                 "workspace_bytes": int(info.workspace_bytes)}
 
-    def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64, full=False):
-        """Workspace bytes; full=True also covers the full adjoint."""
+    def workspace_bytes(self, n_walkers, prec=PN_PREC_FP64, full=False, out_mask=PN_OUT_ALL):
+        """Workspace bytes for pn_eval calls producing the outputs in out_mask
+        (PN_OUT_*) and the value-path adjoint; full=True also covers the full
+        adjoint."""
         b = ctypes.c_size_t()
-        fn = self._lib.pn_workspace_bytes_full if full else self._lib.pn_workspace_bytes
-        _check(fn(self._ctx, int(n_walkers), int(prec), ctypes.byref(b)), "pn_workspace_bytes")
+        if full:
+            st = self._lib.pn_workspace_bytes_full(self._ctx, int(n_walkers), int(prec), ctypes.byref(b))
+        else:
+            st = self._lib.pn_workspace_bytes(self._ctx, int(n_walkers), int(prec), int(out_mask), ctypes.byref(b))
+        _check(st, "pn_workspace_bytes")
         return int(b.value)
 
-    def workspace(self, n_walkers, prec, device, full=False):
+    def workspace(self, n_walkers, prec, device, full=False, out_mask=PN_OUT_ALL):
         import torch
-        need = self.workspace_bytes(n_walkers, prec, full)
+        need = self.workspace_bytes(n_walkers, prec, full, out_mask)
         key = (str(device),)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
@@ -315,7 +322,8 @@ class PauliNetContext:
                 out["lap"] = torch.empty(B, dtype=torch.float64, device=dev)
                 out["eloc"] = torch.empty(B, dtype=torch.float64, device=dev)
         if ws is None:
-            ws = self.workspace(B, prec, dev)
+            derivs = any(out.get(k) is not None for k in ("grad", "lap", "eloc"))
+            ws = self.workspace(B, prec, dev, out_mask=PN_OUT_ALL if derivs else PN_OUT_LOGABS)
         st = self._lib.pn_eval(self._ctx, self._stream(), B, _ptr(r), _ptr(params), int(prec),
                                _ptr(out["logabs"]), _ptr(out["sign"]), _ptr(out.get("grad")),
                                _ptr(out.get("lap")), _ptr(out.get("eloc")), _ptr(ws), ws.numel())

@@ -147,7 +147,7 @@ struct LangWs {
 LangWs lang_layout(const pn_ctx* c, int64_t nw, pn_precision prec) {
   LangWs L{};
   size_t eb = 0;
-  pn_workspace_bytes(c, nw, prec, &eb);
+  pn_workspace_bytes(c, nw, prec, PN_OUT_LOGABS | PN_OUT_GRAD, &eb);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t nc = (size_t)nw * c->d.N * 3 * 8, n1 = (size_t)nw * 8;
   size_t off = 0;

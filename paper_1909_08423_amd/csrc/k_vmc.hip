@@ -270,7 +270,7 @@ struct VmcWs {
 VmcWs vmc_layout(const pn_ctx* c, int64_t nw, pn_precision prec) {
   VmcWs L{};
   size_t eb = 0;
-  pn_workspace_bytes(c, nw, prec, &eb);
+  pn_workspace_bytes(c, nw, prec, PN_OUT_ALL, &eb);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t off = 0;
   L.eval = off;

@@ -126,9 +126,10 @@ bool solve3(double M[3][3], double b[3], double x[3]) {
 }  // namespace
 
 // Workspace plan for `nw` walkers; net_bytes = sizeof of the network type.
-// mode 0: forward; 1: forward + value-path adjoint; 2: also the full
-// adjoint (cotangents on the gradient, Laplacian and E_loc).
-enum { kPlanForward = 0, kPlanValueAdjoint = 1, kPlanFullAdjoint = 2 };
+// mode 0: forward with derivatives; 1: value-path adjoint; 2: full adjoint
+// (cotangents on the gradient, Laplacian and E_loc); 3: value pass only.
+// The tangent pass's buffers exist in modes 0 and 2 only.
+enum { kPlanForward = 0, kPlanValueAdjoint = 1, kPlanFullAdjoint = 2, kPlanValueOnly = 3 };
 
 // chunk size of the full adjoint: the largest T in 1..6 whose tangent-adjoint
 // block keeps its row buffers in LDS; when none fits, the row buffers go to a
@@ -165,7 +166,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
               int64_t min_tile = 256) {
   const Dims& d = c->d;
   const bool fp64 = prec == PN_PREC_FP64;
-  const bool backward = mode >= kPlanValueAdjoint, full = mode == kPlanFullAdjoint;
+  const bool backward = mode == kPlanValueAdjoint || mode == kPlanFullAdjoint, full = mode == kPlanFullAdjoint;
   const size_t tn = fp64 ? sizeof(double) : sizeof(float);
   WsLayout L{};
   L.full = full;
@@ -232,11 +233,12 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
   L.lds_filter = fp64 ? filter_lds_bytes<double>(d, L.filt_rows) : filter_lds_bytes<float>(d, L.filt_rows);
   // determinants of the forward pass through one LU per spin when the
   // expansion allows it (and the caller did not ask for the direct path)
-  L.lowrank = mode == kPlanForward && d.lr && !(d.flags & PN_DET_DIRECT);
+  L.lowrank = (mode == kPlanForward || mode == kPlanValueOnly) && d.lr && !(d.flags & PN_DET_DIRECT);
   L.lds_lr = L.lowrank ? lowrank_tangent_lds_bytes(d, L.T) : 0;
   if (L.lds_lr > kLdsMax) L.lowrank = false;
 
   const int N = d.N, M = d.M, P = d.P, Tp = L.T + 1;
+  const bool tangents = mode == kPlanForward || mode == kPlanFullAdjoint;
   const size_t gsz = (size_t)d.n_up * d.n_up + (size_t)d.n_dn * d.n_dn;
   // bytes per walker of every tile-sized region
   auto per_walker = [&](bool with_bwd) {
@@ -248,7 +250,7 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
     b += (size_t)4 * N * d.DX * tn + 4 * d.DX * tn;
     b += (size_t)N * M * 8 + 8;
     b += (size_t)P * gsz * 8 + (size_t)P * 4 * 8 + (size_t)P * 8 + 8;
-    b += (size_t)L.n_chunks * N * Tp * M * 8 + (size_t)L.n_chunks * Tp * 8 + (size_t)L.n_chunks * 2 * 8;
+    if (tangents) b += (size_t)L.n_chunks * N * Tp * M * 8 + (size_t)L.n_chunks * Tp * 8 + (size_t)L.n_chunks * 2 * 8;
     b += (size_t)N * 3 * 8;
     if (with_bwd) b += (size_t)(d.L + 1) * N * d.DX * tn;
     if (L.lowrank)
@@ -291,9 +293,9 @@ WsLayout plan(const pn_ctx* c, int64_t nw, pn_precision prec, int mode, size_t b
   L.ldet = region((size_t)tile * P * 4 * 8);
   L.wdet = region((size_t)tile * P * 8);
   L.ldpsi = region((size_t)tile * 8);
-  L.ftan = region((size_t)tile * L.n_chunks * N * Tp * M * 8);
-  L.jtan = region((size_t)tile * L.n_chunks * Tp * 8);
-  L.partial = region((size_t)tile * L.n_chunks * 2 * 8);
+  L.ftan = region(tangents ? (size_t)tile * L.n_chunks * N * Tp * M * 8 : 0);
+  L.jtan = region(tangents ? (size_t)tile * L.n_chunks * Tp * 8 : 0);
+  L.partial = region(tangents ? (size_t)tile * L.n_chunks * 2 * 8 : 0);
   // grad scratch for calls that want lap/eloc without grad
   L.adj = region((size_t)tile * std::max(N * 3, 2) * 8);
   L.xval = 0;
@@ -608,12 +610,6 @@ pn_status pn_ctx_create(const pn_system_desc* sys, const pn_net_desc* net, pn_ct
         pidx[(size_t)i * N + j] = p;
         pidx[(size_t)j * N + i] = p;
       }
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j)
-      if (i != j && pair_of(i, j, N, d.n_up) != pidx[(size_t)i * N + j]) {
-        delete c;
-        return PN_ERR_UNSUPPORTED_SHAPE;
-      }
 
   // the expansion as excitations of its first determinant (low-rank path):
   // per (determinant, spin) the hole slots of the first determinant's rows,
@@ -793,21 +789,27 @@ pn_status pn_param_layout(const pn_ctx* c, pn_param_entry* e, int32_t cap, int32
   return k <= cap ? PN_OK : PN_ERR_INVALID_ARG;
 }
 
-pn_status pn_workspace_bytes(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
-  if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
-  *bytes = std::max(plan(c, nw, prec, kPlanForward).total, plan(c, nw, prec, kPlanValueAdjoint).total);
+pn_status pn_workspace_bytes(const pn_ctx* c, int64_t nw, pn_precision prec, uint32_t out_mask, size_t* bytes) {
+  if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16 || (out_mask & ~PN_OUT_ALL))
+    return PN_ERR_INVALID_ARG;
+  // a value-only call plans its own (larger) walker tile, so a workspace for
+  // calls with derivatives covers it as well
+  size_t b = plan(c, nw, prec, kPlanValueOnly).total;
+  if (out_mask & (PN_OUT_GRAD | PN_OUT_LAP | PN_OUT_ELOC)) b = std::max(b, plan(c, nw, prec, kPlanForward).total);
+  if (out_mask & PN_OUT_ADJOINT) b = std::max(b, plan(c, nw, prec, kPlanValueAdjoint).total);
+  *bytes = b;
   return PN_OK;
 }
 
 pn_status pn_workspace_bytes_full(const pn_ctx* c, int64_t nw, pn_precision prec, size_t* bytes) {
   if (!c || !bytes || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
   *bytes = std::max(std::max(plan(c, nw, prec, kPlanForward).total, plan(c, nw, prec, kPlanValueAdjoint).total),
-                    plan(c, nw, prec, kPlanFullAdjoint).total);
+                    std::max(plan(c, nw, prec, kPlanFullAdjoint).total, plan(c, nw, prec, kPlanValueOnly).total));
   return PN_OK;
 }
 
 pn_status pn_eval_plan(const pn_ctx* c, int64_t nw, pn_precision prec, int32_t kind, pn_plan_info* out) {
-  if (!c || !out || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16 || kind < 0 || kind > 2)
+  if (!c || !out || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16 || kind < 0 || kind > 3)
     return PN_ERR_INVALID_ARG;
   const WsLayout L = plan(c, nw, prec, kind);
   memset(out, 0, sizeof(*out));
@@ -825,7 +827,7 @@ pn_status pn_eval(const pn_ctx* c, hipStream_t s, int64_t nw, const double* r, c
   if (!c || nw < 0 || prec < PN_PREC_FP64 || prec > PN_PREC_NET_BF16) return PN_ERR_INVALID_ARG;
   if (nw == 0) return PN_OK;
   if (!r || !params || !logabs || !sign || !ws) return PN_ERR_INVALID_ARG;
-  WsLayout L = plan(c, nw, prec, kPlanForward);
+  WsLayout L = plan(c, nw, prec, (grad || lap || eloc) ? kPlanForward : kPlanValueOnly);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
   if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
   return eval_impl(c, s, nw, r, params, prec, logabs, sign, grad, lap, eloc, static_cast<char*>(ws), L);
@@ -839,7 +841,7 @@ pn_status pn_eval_noalloc(const pn_ctx* c, hipStream_t s, int64_t nw, const doub
   char* base = static_cast<char*>(scratch_of(c->device));
   if (!base) return PN_ERR_DEVICE;
   // walker tiles sized for the static scratch (down to one walker)
-  WsLayout L = plan(c, nw, prec, kPlanForward, kScratchBytes, 1);
+  WsLayout L = plan(c, nw, prec, (grad || lap || eloc) ? kPlanForward : kPlanValueOnly, kScratchBytes, 1);
   if (L.total > kScratchBytes) return PN_ERR_WORKSPACE_TOO_SMALL;
   if (L.lds_tangent > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
   return eval_impl(c, s, nw, r, params, prec, logabs, sign, grad, lap, eloc, base, L);
@@ -1006,7 +1008,7 @@ pn_status pn_eval_backward_cusp(const pn_ctx* c, hipStream_t s, int64_t nw, cons
   if (c->n_cusp_on == 0) return PN_OK;  // no corrected orbital: the gradient is zero
   const Dims& d = c->d;
   if (cusp_grad_lds_bytes(d) > kLdsMax) return PN_ERR_UNSUPPORTED_SHAPE;
-  const bool fp64 = prec == PN_PREC_FP64, bf16 = prec == PN_PREC_NET_BF16;
+  const bool fp64 = prec == PN_PREC_FP64;
   WsLayout L = plan(c, nw, prec, kPlanValueAdjoint);
   if (ws_bytes < L.total) return PN_ERR_WORKSPACE_TOO_SMALL;
   char* base = static_cast<char*>(ws);

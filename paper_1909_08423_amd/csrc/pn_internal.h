@@ -155,7 +155,7 @@ struct WsLayout {
 
 constexpr int kSlotsTanAdj = 512;  // blocks (and gradient slots) of the tangent adjoint
 
-constexpr int kGeoStride(int N) { return 4 + 6 * N; }
+constexpr int kGeoStride(int N) { return 4 + 6 * N; }  // V, gamma, lap_gamma, pad, N*(grad3, hess3)
 
 // Electrons whose coordinates a chunk of T coordinates starting at a
 // multiple of T can hold: exactly T / 3 when 3 divides T (chunks then start
@@ -163,23 +163,6 @@ constexpr int kGeoStride(int N) { return 4 + 6 * N; }
 __host__ __device__ constexpr int chunk_elecs_max(int N, int T) {
   return (T % 3 == 0 ? T / 3 : T / 3 + 2) < N ? (T % 3 == 0 ? T / 3 : T / 3 + 2) : N;
 }
-
-// Index of the electron pair {i, j} (i != j) in the pair tables: same-spin
-// pairs first (up-up, then down-down, each in row-major order of the upper
-// triangle), then opposite-spin pairs (up electron major).  This is the
-// order in which the context enumerates them (its pair_index table holds
-// the same numbers; pn_ctx_create checks that they agree); kernels use the
-// closed form where a table read would sit on a load's address path.
-__host__ __device__ __forceinline__ int pair_of(int i, int j, int N, int NU) {
-  const int a = i < j ? i : j, b = i < j ? j : i, ND = N - NU;
-  const int nuu = NU * (NU - 1) / 2;
-  if (b < NU) return a * NU - a * (a + 1) / 2 + (b - a - 1);
-  if (a >= NU) {
-    const int x = a - NU, y = b - NU;
-    return nuu + x * ND - x * (x + 1) / 2 + (y - x - 1);
-  }
-  return nuu + ND * (ND - 1) / 2 + a * ND + (b - NU);
-}  // V, gamma, lap_gamma, pad, N*(grad3, hess3)
 
 }  // namespace pn
 

@@ -81,6 +81,39 @@ def test_value_only_matches_full(pn):
     np.testing.assert_array_equal(a["sign"], b["sign"])
 
 
+@pytest.mark.parametrize("idx", [2, 5])
+def test_value_only_workspace(pn, idx):
+    """pn_workspace_bytes with out_mask PN_OUT_LOGABS sizes a workspace for
+    value-only calls (no tangent buffers): smaller than the one for calls
+    with derivatives and the value-path adjoint, enough for a value-only pn_eval (ln|psi| and sign bit
+    for bit those of the full call, the low-rank determinant path included),
+    and refused for a call with derivatives; bits outside PN_OUT_ALL are
+    invalid arguments."""
+    w = make_config(idx, n_walkers=37)
+    announce(f"value-only workspace, workload {idx}")
+    ctx = pn.PauliNetContext(w.system, w.net)
+    prec = pn.PN_PREC_NET_FP32 if idx == 5 else pn.PN_PREC_FP64
+    B = len(w.walkers)
+    small = ctx.workspace_bytes(B, prec, out_mask=pn.PN_OUT_LOGABS)
+    big = ctx.workspace_bytes(B, prec, out_mask=pn.PN_OUT_ALL)
+    fwd = ctx.workspace_bytes(B, prec, out_mask=pn.PN_OUT_LOGABS | pn.PN_OUT_ELOC)
+    assert small < fwd <= big
+    assert ctx.plan(B, prec, pn.PLAN_VALUE_ONLY)["workspace_bytes"] <= small
+    r = torch.tensor(w.walkers, dtype=torch.float64, device="cuda")
+    th = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    a = ctx.eval(r, th, prec, want_derivs=False, ws=ws)
+    b = ctx.eval(r, th, prec)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a["logabs"].cpu().numpy(), b["logabs"].cpu().numpy())
+    np.testing.assert_array_equal(a["sign"].cpu().numpy(), b["sign"].cpu().numpy())
+    with pytest.raises(pn.PauliNetError, match="(?i)workspace"):
+        ctx.eval(r, th, prec, ws=ws)
+    with pytest.raises(pn.PauliNetError):
+        ctx.workspace_bytes(B, prec, out_mask=32)
+    ctx.close()
+
+
 def test_deterministic_bits(pn):
     w = make_config(3, n_walkers=300)
     announce("determinism, workload 3")
