@@ -51,6 +51,7 @@ namespace pn {
 namespace {
 
 constexpr int kWaves = kThreads / 64;
+constexpr int kItems = 8;  // step-1 items per thread of k_lr_tangent kept in registers
 constexpr double kRatioMax = 1e4;
 
 __device__ __forceinline__ void wave_sync() {
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_lr_list(int64_t nw, const int* __restr
 // Element offsets of the tangent kernel's LDS regions (doubles, then ints).
 struct LrLds {
   int gsz, thsz, bsz, R0, R1;
-  size_t G0, TH, TB, LT, BM, SS, YY, TRN, TRN2, GPA, QACC, DELTA, DINV, WD, LAPC, SQC, SCAL, n_dbl;
+  size_t G0, TH, TB, LT, BM, SS, YY, TRN, TRN2, GPA, QACC, DELTA, DINV, WD, LAPC, SQC, SCAL, PF, n_dbl;
   size_t ROWORB, n_int;
 };
 
@@ -266,21 +267,22 @@ __host__ __device__ inline LrLds lr_lds(const Dims& d, int T) {
   o.YY = take(o.thsz);
   o.TRN = take((size_t)T * 2);
   o.TRN2 = take((size_t)T * 2);
-  o.GPA = take((size_t)d.P * T);
-  o.QACC = take(d.P);
+  o.GPA = take((size_t)d.P * T * 2);
+  o.QACC = take((size_t)d.P * 2);
   o.DELTA = take(d.P);
   o.DINV = take((size_t)d.P * 2 * kMaxExc * kMaxExc);
   o.WD = take(d.P);
   o.LAPC = take(T);
   o.SQC = take(T);
   o.SCAL = take(8);
+  o.PF = take((size_t)2 * d.N * d.M);
   o.n_dbl = off;
   o.ROWORB = 0;
   o.n_int = o.R0 + o.R1;
   return o;
 }
 
-__global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
+__global__ __launch_bounds__(kThreads, 2) void k_lr_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
                                                          const double* __restrict__ geo,
                                                          const double* __restrict__ phi,
                                                          const double* __restrict__ fval,
@@ -307,14 +309,15 @@ __global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, in
   double* YY = sm + o.YY;      // [thsz] sum_a d2_a Theta on the virtual rows
   double* TRN = sm + o.TRN;    // [T][2] tr N_a
   double* TRN2 = sm + o.TRN2;  // [T][2] tr N_a^2
-  double* GPA = sm + o.GPA;    // [P][T] d_a ln|D_p| over both spins
-  double* QACC = sm + o.QACC;  // [P] sum_a tr((D^-1 Xi_a)^2) over both spins
+  double* GPA = sm + o.GPA;    // [P][T][2] d_a ln|D_p|, each spin's minor
+  double* QACC = sm + o.QACC;  // [P][2] sum_a tr((D^-1 Xi_a)^2), each spin
   double* DELTA = sm + o.DELTA;
   double* DI = sm + o.DINV;    // [P][2][kMaxExc^2]
   double* WD = sm + o.WD;      // [P]
   double* LAPC = sm + o.LAPC;
   double* SQC = sm + o.SQC;
   double* SCAL = sm + o.SCAL;  // lap, |grad|^2, sum tr N^2 (up, down), tr Lambda[occ] (up, down)
+  double* PF = sm + o.PF;      // [2][N][M] phi_mu(r_i) and f_{i mu} of the walker
   int* ROWORB = reinterpret_cast<int*>(sm + o.n_dbl);
 
   const int gsz = o.gsz, thsz = o.thsz, bsz = o.bsz;
@@ -333,84 +336,170 @@ __global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, in
   for (int q = tid; q < P * 2 * kMaxExc * kMaxExc; q += nth) DI[q] = dinv[w * P * 2 * kMaxExc * kMaxExc + q];
   for (int q = tid; q < P; q += nth) {
     WD[q] = wdet[w * P + q];
-    QACC[q] = 0.0;
+    QACC[2 * q] = QACC[2 * q + 1] = 0.0;
   }
   for (int q = tid; q < o.R0 + o.R1; q += nth) {
     const int s = q >= o.R0, r = s ? q - o.R0 : q, n = ns(s);
     ROWORB[q] = r < n ? (s ? t.det_dn[r] : t.det_up[r]) : t.lr_vorb[s * M + (r - n)];
   }
   if (tid < 8) SCAL[tid] = 0.0;
+  for (int q = tid; q < N * M; q += nth) {
+    PF[q] = phi[((size_t)w * N * M + q) * 7];
+    PF[N * M + q] = fval[(size_t)w * N * M + q];
+  }
   __syncthreads();
 
   const double* ph = phi + w * N * M * 7;
   const double* fv = fval + w * N * M;
   const double* g = geo + w * kGeoStride(N);
-  const int Tp = T + 1;
+  const int Tp = T + 1, NTM = N * Tp * M;
+  // the first chunk's tangents of the step-1 items held in registers, and
+  // the items' (i, column, mu) decoded once (the same in every chunk; M <= 128
+  // and columns <= 17 fit their 8-bit fields)
+  double ftv[kItems];
+  int pk[kItems];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int q = tid + u * nth;
+    if (q >= NTM) break;
+    ftv[u] = ftan[(size_t)w * n_chunks * NTM + q];
+    pk[u] = ((q / (Tp * M)) << 16) | (((q / M) % Tp) << 8) | (q % M);
+  }
   for (int chunk = 0; chunk < n_chunks; ++chunk) {
     const int a0 = chunk * T, Tc = min(T, 3 * N - a0);
-    const double* ft = ftan + ((size_t)w * n_chunks + chunk) * N * Tp * M;
+    const double* ft = ftan + ((size_t)w * n_chunks + chunk) * NTM;
     const double* jt = jtan + ((size_t)w * n_chunks + chunk) * Tp;
     // 1. table derivatives T_a[mu][i] and the chunk's part of the table
-    //    Laplacian, read in the memory order of the network tangents
-    for (int q = tid; q < N * Tp * M; q += nth) {
-      const int i = q / (Tp * M), col = (q / M) % Tp, mu = q % M;
-      const double* pj = ph + ((size_t)i * M + mu) * 7;
-      const double f = fv[i * M + mu];
-      if (col < Tc) {
-        const int a = a0 + col, k = a / 3, al = a % 3;
-        double v = pj[0] * ft[q];
-        if (k == i) v += pj[1 + al] * f;
-        TB[((size_t)col * M + mu) * N + i] = v;
-      } else if (col == T) {
-        double v = pj[0] * ft[q];
-        for (int c2 = 0; c2 < Tc; ++c2) {
-          const int a = a0 + c2, k = a / 3, al = a % 3;
-          if (k != i) continue;
-          v += pj[4 + al] * f + 2.0 * pj[1 + al] * ft[((size_t)i * Tp + c2) * M + mu];
+    //    Laplacian, read in the memory order of the network tangents.  A
+    //    thread's items (i, column, mu) are the same in every chunk: phi
+    //    and f come from LDS (copied once per walker), and the tangents of
+    //    the first kItems items for the next chunk are requested into
+    //    registers at the end of this step, so the HBM latency overlaps
+    //    steps 2 to 5.
+    {
+#pragma unroll
+      for (int u = 0; u < kItems; ++u) {
+        const int q = tid + u * nth;
+        if (q >= NTM) break;
+        const int i = pk[u] >> 16, col = (pk[u] >> 8) & 255, mu = pk[u] & 255;
+        const double* pj = ph + ((size_t)i * M + mu) * 7;
+        const double f = PF[N * M + i * M + mu];
+        if (col < Tc) {
+          const int a = a0 + col, k = a / 3, al = a % 3;
+          double v = PF[i * M + mu] * ftv[u];
+          if (k == i) v += pj[1 + al] * f;
+          TB[((size_t)col * M + mu) * N + i] = v;
+        } else if (col == T) {
+          double v = PF[i * M + mu] * ftv[u];
+          for (int c2 = 0; c2 < Tc; ++c2) {
+            const int a = a0 + c2, k = a / 3, al = a % 3;
+            if (k != i) continue;
+            v += pj[4 + al] * f + 2.0 * pj[1 + al] * ft[((size_t)i * Tp + c2) * M + mu];
+          }
+          LT[mu * N + i] += v;
         }
-        LT[mu * N + i] += v;
+      }
+      for (int q = tid + kItems * nth; q < NTM; q += nth) {  // items past the register-resident ones
+        const int i = q / (Tp * M), col = (q / M) % Tp, mu = q % M;
+        const double* pj = ph + ((size_t)i * M + mu) * 7;
+        const double f = fv[i * M + mu];
+        if (col < Tc) {
+          const int a = a0 + col, k = a / 3, al = a % 3;
+          double v = pj[0] * ft[q];
+          if (k == i) v += pj[1 + al] * f;
+          TB[((size_t)col * M + mu) * N + i] = v;
+        } else if (col == T) {
+          double v = pj[0] * ft[q];
+          for (int c2 = 0; c2 < Tc; ++c2) {
+            const int a = a0 + c2, k = a / 3, al = a % 3;
+            if (k != i) continue;
+            v += pj[4 + al] * f + 2.0 * pj[1 + al] * ft[((size_t)i * Tp + c2) * M + mu];
+          }
+          LT[mu * N + i] += v;
+        }
+      }
+      if (chunk + 1 < n_chunks) {
+        const double* ftn = ft + (size_t)NTM;  // the next chunk's tangents follow this chunk's
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          const int q = tid + u * nth;
+          if (q >= NTM) break;
+          ftv[u] = ftn[q];
+        }
       }
     }
     __syncthreads();
-    // 2. B_a = T_a G_0 on the first determinant's rows and the virtual rows
-    for (int q = tid; q < Tc * bsz; q += nth) {
-      const int col = q / bsz, rem = q % bsz;
-      const int s = rem >= sB1, rr = rem - soffB(s), n = ns(s);
-      const int r = rr / n, k = rr % n;
-      const double* tb = TB + ((size_t)col * M + ROWORB[s * o.R0 + r]) * N + e0s(s);
-      const double* Gs = G0s + (s ? nu * nu : 0);
-      double acc = 0.0;
-      for (int i = 0; i < n; ++i) acc += tb[i] * Gs[i * n + k];
-      BM[(size_t)col * bsz + rem] = acc;
+    // 2. B_a = T_a G_0 on the first determinant's rows and the virtual rows;
+    //    an item is four consecutive slots k of one row (four independent
+    //    sums sharing the row's reads)
+    {
+      const int nq0 = o.R0 * ((nu + 3) / 4), nq1 = o.R1 * ((nd + 3) / 4), nq = nq0 + nq1;
+      for (int q = tid; q < Tc * nq; q += nth) {
+        const int col = q / nq, rem = q % nq;
+        const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nk4 = (n + 3) / 4;
+        const int r = rq / nk4, k0 = (rq % nk4) * 4;
+        const double* tb = TB + ((size_t)col * M + ROWORB[s * o.R0 + r]) * N + e0s(s);
+        const double* Gs = G0s + (s ? nu * nu : 0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < n; ++i) {
+          const double x = tb[i];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] += x * Gs[i * n + min(k0 + u, n - 1)];
+        }
+        double* B = BM + (size_t)col * bsz + soffB(s) + r * n;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < n) B[k0 + u] = acc[u];
+      }
     }
     __syncthreads();
-    // 3. Xi_a = B_a - Theta N_a on the virtual rows (in place), tr N_a, tr N_a^2
-    for (int q = tid; q < Tc * thsz + Tc * 2; q += nth) {
-      if (q < Tc * thsz) {
-        const int col = q / thsz, rem = q % thsz;
-        const int s = rem >= sT1, rr = rem - soffT(s), n = ns(s);
-        const int v = rr / n, k = rr % n;
+    // 3. Xi_a = B_a - Theta N_a on the virtual rows (in place; an item is
+    //    four consecutive slots of one row), and tr N_a, tr N_a^2 per
+    //    (coordinate, spin) by one wavefront (lane k: row k), summed across
+    //    the lanes in a fixed order
+    {
+      const int nq0 = d.nv[0] * ((nu + 3) / 4), nq1 = d.nv[1] * ((nd + 3) / 4), nq = nq0 + nq1;
+      for (int q = tid; q < Tc * nq; q += nth) {
+        const int col = q / nq, rem = q % nq;
+        const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nk4 = (n + 3) / 4;
+        const int v = rq / nk4, k0 = (rq % nk4) * 4;
         double* B = BM + (size_t)col * bsz + soffB(s);
         const double* th = THs + soffT(s) + v * n;
-        double acc = B[(n + v) * n + k];
-        for (int l = 0; l < n; ++l) acc -= th[l] * B[l * n + k];
-        B[(n + v) * n + k] = acc;
-      } else {
-        const int col = (q - Tc * thsz) / 2, s = (q - Tc * thsz) % 2, n = ns(s);
+        double acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = B[(n + v) * n + min(k0 + u, n - 1)];
+        for (int l = 0; l < n; ++l) {
+          const double x = th[l];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] -= x * B[l * n + min(k0 + u, n - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < n) B[(n + v) * n + k0 + u] = acc[u];
+      }
+      const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
+      for (int cs = wv; cs < Tc * 2; cs += nwv) {
+        const int col = cs / 2, s = cs % 2, n = ns(s);
         const double* B = BM + (size_t)col * bsz + soffB(s);
         double tr = 0.0, tr2 = 0.0;
-        for (int k = 0; k < n; ++k) {
-          tr += B[k * n + k];
-          for (int l = 0; l < n; ++l) tr2 += B[k * n + l] * B[l * n + k];
+        if (lane < n) {
+          tr = B[lane * n + lane];
+          for (int l = 0; l < n; ++l) tr2 += B[lane * n + l] * B[l * n + lane];
         }
-        TRN[col * 2 + s] = tr;
-        TRN2[col * 2 + s] = tr2;
+        for (int off = 32; off > 0; off >>= 1) {
+          tr += __shfl_xor(tr, off, 64);
+          tr2 += __shfl_xor(tr2, off, 64);
+        }
+        if (lane == 0) {
+          TRN[col * 2 + s] = tr;
+          TRN2[col * 2 + s] = tr2;
+        }
       }
     }
     __syncthreads();
     // 4. S += sum_a Xi_a N_a (virtual rows x all slots), and per member
     //    d_a ln|D_p| and tr((D_p^-1 Xi_a)^2)
-    for (int q = tid; q < thsz + P; q += nth) {
+    for (int q = tid; q < thsz + 2 * P; q += nth) {
       if (q < thsz) {
         const int s = q >= sT1, rr = q - soffT(s), n = ns(s);
         const int v = rr / n, h = rr % n;
@@ -421,18 +510,19 @@ __global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, in
         }
         SS[q] = acc;
       } else {
-        const int p = q - thsz;
-        double qsum = QACC[p];
+        // member p, spin s: d_a ln|det D_p| = tr(D^-1 Xi_a[v][h]) and
+        // tr((D^-1 Xi_a[v][h])^2) for the chunk's coordinates
+        const int p = (q - thsz) >> 1, s = (q - thsz) & 1;
+        const int k = t.lr_k[p * 2 + s];
+        double qsum = QACC[p * 2 + s];
+        const int n = ns(s);
+        const int* hl = t.lr_hole + (p * 2 + s) * kMaxExc;
+        const int* pt = t.lr_part + (p * 2 + s) * kMaxExc;
+        const double* Di = DI + (p * 2 + s) * kMaxExc * kMaxExc;
         for (int col = 0; col < Tc; ++col) {
-          double gp = TRN[col * 2] + TRN[col * 2 + 1];
-          for (int s = 0; s < 2; ++s) {
-            const int k = t.lr_k[p * 2 + s];
-            if (k == 0) continue;
-            const int n = ns(s);
-            const int* hl = t.lr_hole + (p * 2 + s) * kMaxExc;
-            const int* pt = t.lr_part + (p * 2 + s) * kMaxExc;
+          double gp = 0.0;
+          if (k > 0) {
             const double* B = BM + (size_t)col * bsz + soffB(s);
-            const double* Di = DI + (p * 2 + s) * kMaxExc * kMaxExc;
             double X[kMaxExc][kMaxExc], Mx[kMaxExc][kMaxExc];
 #pragma unroll
             for (int j = 0; j < kMaxExc; ++j)
@@ -454,25 +544,36 @@ __global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, in
               for (int l2 = 0; l2 < kMaxExc; ++l2) qsum += Mx[l][l2] * Mx[l2][l];
             }
           }
-          GPA[p * T + col] = gp;
+          GPA[(p * T + col) * 2 + s] = gp;
         }
-        QACC[p] = qsum;
+        QACC[p * 2 + s] = qsum;
       }
     }
     __syncthreads();
-    // 5. determinant sum per coordinate, gamma and J
-    if (tid < Tc) {
-      const int col = tid, a = a0 + col, k = a / 3, al = a % 3;
-      double dpsi = 0.0, wsq = 0.0;
-      for (int p = 0; p < P; ++p) {
-        const double gp = GPA[p * T + col];
-        dpsi += WD[p] * gp;
-        wsq += WD[p] * gp * gp;
+    // 5. determinant sum per coordinate (one wavefront per coordinate, lanes
+    //    over members, summed across the lanes in a fixed order), gamma and J
+    {
+      const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
+      for (int col = wv; col < Tc; col += nwv) {
+        const int a = a0 + col, k = a / 3, al = a % 3;
+        const double trn = TRN[col * 2] + TRN[col * 2 + 1];
+        double dpsi = 0.0, wsq = 0.0;
+        for (int p = lane; p < P; p += 64) {
+          const double gp = trn + GPA[(p * T + col) * 2] + GPA[(p * T + col) * 2 + 1];
+          dpsi += WD[p] * gp;
+          wsq += WD[p] * gp * gp;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          dpsi += __shfl_xor(dpsi, off, 64);
+          wsq += __shfl_xor(wsq, off, 64);
+        }
+        if (lane == 0) {
+          const double gtot = g[4 + 6 * k + al] + jt[col] + dpsi;
+          grad[w * N * 3 + a] = gtot;
+          LAPC[col] = wsq - dpsi * dpsi + g[4 + 6 * k + 3 + al];
+          SQC[col] = gtot * gtot;
+        }
       }
-      const double gtot = g[4 + 6 * k + al] + jt[col] + dpsi;
-      grad[w * N * 3 + a] = gtot;
-      LAPC[col] = wsq - dpsi * dpsi + g[4 + 6 * k + 3 + al];
-      SQC[col] = gtot * gtot;
     }
     __syncthreads();
     if (tid == 0) {
@@ -524,7 +625,7 @@ __global__ __launch_bounds__(kThreads) void k_lr_tangent(Dims d, DevTables t, in
   __syncthreads();
   // 8. each member's Laplacian of ln|det|, both spins
   for (int p = tid; p < P; p += nth) {
-    double dl = SCAL[4] + SCAL[5] - SCAL[2] - SCAL[3] - QACC[p];
+    double dl = SCAL[4] + SCAL[5] - SCAL[2] - SCAL[3] - QACC[2 * p] - QACC[2 * p + 1];
     for (int s = 0; s < 2; ++s) {
       const int k = t.lr_k[p * 2 + s];
       if (k == 0) continue;
