@@ -58,6 +58,32 @@ __device__ __forceinline__ void dma16(uint4* __restrict__ dst, const uint4* __re
     if (b + lane < n) __builtin_amdgcn_global_load_lds(src + b + lane, dst + b, 16, 0, 0);
 }
 
+// Head activation as the epilogue of the product that feeds it (chunks of
+// three coordinates in the FP32 tile layout, where a lane's four results are
+// the four columns of one row group: electron i = 4 rt + lane / 16 for the
+// backflow head, the summed embedding for the Jastrow head):
+//   y_a = s1 v_a (a < 3),   y_L = s1 v_L + s2 sum_a v_a^2
+// with the value pass's slopes s1 = ssp'(u), s2 = ssp''(u) of the feature.
+template <typename TN>
+struct HeadAct {
+  const TN* s;  // [2][rows][DX] slopes (s1 block, then s2 block)
+  int n_rows, DX;
+  bool per_row;  // backflow: slopes per electron; Jastrow: one row
+  template <typename A>
+  __device__ void operator()(int rt, int col, A& c) const {
+    const int i = per_row ? min(4 * rt + (((int)threadIdx.x & 63) >> 4), n_rows - 1) : 0;
+    const TN s1 = s[i * DX + col], s2 = s[(n_rows + i) * DX + col];
+    TN sq = 0;
+    sq += c[0] * c[0];
+    sq += c[1] * c[1];
+    sq += c[2] * c[2];
+    c[0] = s1 * c[0];
+    c[1] = s1 * c[1];
+    c[2] = s1 * c[2];
+    c[3] = s1 * c[3] + s2 * sq;
+  }
+};
+
 // BF16 is a template parameter so that the FP32 and FP64 instantiations
 // carry no BF16 operand code (smaller kernels, fewer instruction-cache
 // misses).  NT threads per block: 256 with two blocks per CU (80 KB of LDS
@@ -450,7 +476,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // The heads' activation slopes (kappa [2][2][N][DX], then eta [2][2][DX])
   // go to the staging region, which the layers no longer need; the copy is
   // issued before the Jastrow sum so its latency overlaps that work.
-  const bool hstage = STAGE && d.n_ee * DZ + 2 * nce_max * NP * DZ >= 4 * N * DX + 4 * DX;
+  // chunks of three coordinates in FP32 layout apply the head activations in
+  // the products' epilogues (slopes read from global memory, no staging)
+  constexpr bool kFuse = C == 4 && sizeof(TN) == 4;
+  const bool hstage = !kFuse && STAGE && d.n_ee * DZ + 2 * nce_max * NP * DZ >= 4 * N * DX + 4 * DX;
   if (hstage) {
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6, nwv = (int)blockDim.x >> 6;
     dma16(reinterpret_cast<uint4*>(wvs), reinterpret_cast<const uint4*>(kcoef + w * 4 * N * DX), 4 * N * DX / V, lane,
@@ -523,24 +552,40 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   } else {
     for (int col = threadIdx.x; col < C; col += blockDim.x) jt[col] = 0.0;
   }
-  if (do_k)
-    gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
-  else
-    for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
-  __builtin_amdgcn_s_waitcnt(0);  // the staged activation slopes have landed
-  __syncthreads();
-  if (do_j) gemm_mfma<TN, true>(S0, LDX, C, DX, P + pl.eW1, DX, S1, LDX, false, bf16);
-  if (do_k) act_k(KT, 0);
-  __syncthreads();
-  if (do_j) act_j(S1, 0);
-  if (do_k) gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
-  __syncthreads();
-  if (do_j) gemm_mfma<TN, true>(S1, LDX, C, DX, P + pl.eW2, DX, S0, LDX, false, bf16);
-  if (do_k) act_k(XT, 1);
-  __syncthreads();
-  if (do_j) act_j(S0, 1);
-  if (do_k) gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
-  __syncthreads();
+  if constexpr (kFuse) {
+    const HeadAct<TN> k0{kcoef + (w * 2 + 0) * 2 * N * DX, N, DX, true}, k1{kcoef + (w * 2 + 1) * 2 * N * DX, N, DX, true};
+    const HeadAct<TN> j0{ecoef + (w * 2 + 0) * 2 * DX, 1, DX, false}, j1{ecoef + (w * 2 + 1) * 2 * DX, 1, DX, false};
+    if (do_k)
+      gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16, k0);
+    else
+      for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
+    __syncthreads();
+    if (do_j) gemm_mfma<TN, true>(S0, LDX, C, DX, P + pl.eW1, DX, S1, LDX, false, bf16, j0);
+    if (do_k) gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16, k1);
+    __syncthreads();
+    if (do_j) gemm_mfma<TN, true>(S1, LDX, C, DX, P + pl.eW2, DX, S0, LDX, false, bf16, j1);
+    if (do_k) gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+    __syncthreads();
+  } else {
+    if (do_k)
+      gemm_mfma<TN, true>(XT, LDX, R, DX, P + pl.kW1, DX, KT, LDX, false, bf16);
+    else
+      for (int q = threadIdx.x; q < R * M; q += blockDim.x) ft[q] = 0.0;
+    __builtin_amdgcn_s_waitcnt(0);  // the staged activation slopes have landed
+    __syncthreads();
+    if (do_j) gemm_mfma<TN, true>(S0, LDX, C, DX, P + pl.eW1, DX, S1, LDX, false, bf16);
+    if (do_k) act_k(KT, 0);
+    __syncthreads();
+    if (do_j) act_j(S1, 0);
+    if (do_k) gemm_mfma<TN, true>(KT, LDX, R, DX, P + pl.kW2, DX, XT, LDX, false, bf16);
+    __syncthreads();
+    if (do_j) gemm_mfma<TN, true>(S1, LDX, C, DX, P + pl.eW2, DX, S0, LDX, false, bf16);
+    if (do_k) act_k(XT, 1);
+    __syncthreads();
+    if (do_j) act_j(S0, 1);
+    if (do_k) gemm_mfma_cols<TN>(XT, LDX, R, DX, P + pl.kW3, M, KT, LDX, false, bf16);
+    __syncthreads();
+  }
   if (do_j) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int col = wv; col < C; col += (int)(blockDim.x >> 6)) {

@@ -26,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pn {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -52,6 +54,14 @@ template <>
 struct MfmaTile<float> {
   typedef v4f acc_t;
   __device__ static int row_of(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Output epilogue: called as epi(row_tile, column, acc) on each 16 x 16
+// result just before it is stored (this lane's four elements of `column`,
+// layout as above).  NoEpi stores the product as is.
+struct NoEpi {
+  template <typename A>
+  __device__ void operator()(int, int, A&) const {}
 };
 
 // One wavefront: C += A_tile(16 x I) * B_slab(I x 16), operands in registers
@@ -114,11 +124,12 @@ struct MfmaChain<float, KQ> {
 // DUAL: a second product on a row window, X2[row - lo] * W2 for output rows
 // [lo, lo + n), summed into the same tiles as the full product X * W (its
 // weight slab is read together with the first one).
-template <typename TN, int KQ, bool WT = false, bool WIN = false, bool PAIR = false, bool DUAL = false>
+template <typename TN, int KQ, bool WT = false, bool WIN = false, bool PAIR = false, bool DUAL = false,
+          typename EPI = NoEpi>
 __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, const TN* __restrict__ W, int ldw, int O,
                                             int ncol, TN* Y, int ldy, bool accumulate, bool bf16, int lo = 0,
                                             int n = 0, const TN* X2 = nullptr, int ldx2 = 0,
-                                            const TN* __restrict__ W2 = nullptr) {
+                                            const TN* __restrict__ W2 = nullptr, EPI epi = EPI()) {
   typedef typename MfmaTile<TN>::acc_t acc_t;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
@@ -136,6 +147,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
     rt_step = nwv / n_ct;
   }
   constexpr bool kPair = PAIR && !WIN && sizeof(TN) == 4;
+  constexpr bool kEpi = !std::is_same<EPI, NoEpi>::value;
   // A fragment of row tile rt: 16-byte reads, so each group of 8 lanes
   // covers every LDS bank once (rows are padded by 16 bytes); element-wise
   // reads of the same rows hit each bank up to four times.  Rows and
@@ -228,6 +240,10 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
         cb = MfmaChain<TN, KQ>::run(afb, bfrag, cb, bf16);
         ca = second(rt, ca);
         cb = second(rtb, cb);
+        if constexpr (kEpi) {
+          epi(rt, col, ca);
+          epi(rtb, col, cb);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = MfmaTile<TN>::row_of(lane, v);
@@ -249,6 +265,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
         }
         c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
         c = second(rt, c);
+        if constexpr (kEpi) epi(rt, col, c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -263,6 +280,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
       }
       c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
       c = second(rt, c);
+      if constexpr (kEpi) epi(rt, col, c);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -295,16 +313,26 @@ __device__ __forceinline__ void gemm_mfma_cols(const TN* X, int ldx, int rows, i
   }
 }
 
-template <typename TN, bool PAIR = false>
+template <typename TN, bool PAIR = false, typename EPI = NoEpi>
 __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I, const TN* __restrict__ W, int O,
-                                          TN* Y, int ldy, bool accumulate, bool bf16) {
+                                          TN* Y, int ldy, bool accumulate, bool bf16, EPI epi = EPI()) {
   switch (I) {
-    case 16: gemm_mfma_k<TN, 4, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    case 32: gemm_mfma_k<TN, 8, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    case 64: gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16); break;
-    default:
+    case 16:
+      gemm_mfma_k<TN, 4, false, false, PAIR, false, EPI>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16, 0, 0,
+                                                           nullptr, 0, nullptr, epi);
+      break;
+    case 32:
+      gemm_mfma_k<TN, 8, false, false, PAIR, false, EPI>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16, 0, 0,
+                                                           nullptr, 0, nullptr, epi);
+      break;
+    case 64:
+      gemm_mfma_k<TN, 16, false, false, PAIR, false, EPI>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16, 0, 0,
+                                                            nullptr, 0, nullptr, epi);
+      break;
+    default:  // the epilogue acts on the sum of both halves
       gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
-      gemm_mfma_k<TN, 16, false, false, PAIR>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy, true, bf16);
+      gemm_mfma_k<TN, 16, false, false, PAIR, false, EPI>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy,
+                                                            true, bf16, 0, 0, nullptr, 0, nullptr, epi);
       break;
   }
 }
