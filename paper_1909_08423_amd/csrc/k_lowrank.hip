@@ -43,6 +43,8 @@
 //                the gradient and the walker's Laplacian / |grad|^2 partials.
 #include <math.h>
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "pn_internal.h"
@@ -51,7 +53,6 @@ namespace pn {
 namespace {
 
 constexpr int kWaves = kThreads / 64;
-constexpr int kItems = 8;  // step-1 items per thread of k_lr_tangent kept in registers
 constexpr double kRatioMax = 1e4;
 
 __device__ __forceinline__ void wave_sync() {
@@ -282,7 +283,13 @@ __host__ __device__ inline LrLds lr_lds(const Dims& d, int T) {
   return o;
 }
 
-__global__ __launch_bounds__(kThreads, 2) void k_lr_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
+// WIDE: spins of 8 or more electrons, blocks of over 40 KB of LDS (at most
+// two per CU, so a wave may hold up to 256 registers): slot blocking in
+// steps 2 and 3 and the next chunk's tangents of the first 8 step-1 items
+// requested ahead.  Otherwise one slot per item, no prefetch, and at most
+// 128 registers (four blocks per CU).
+template <bool WIDE>
+__global__ __launch_bounds__(kThreads, WIDE ? 2 : 4) void k_lr_tangent(Dims d, DevTables t, int64_t nw, int T, int n_chunks,
                                                          const double* __restrict__ geo,
                                                          const double* __restrict__ phi,
                                                          const double* __restrict__ fval,
@@ -356,6 +363,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_lr_tangent(Dims d, DevTables t,
   // the first chunk's tangents of the step-1 items held in registers, and
   // the items' (i, column, mu) decoded once (the same in every chunk; M <= 128
   // and columns <= 17 fit their 8-bit fields)
+  constexpr int kItems = WIDE ? 8 : 1;  // step-1 items per thread kept in registers
   double ftv[kItems];
   int pk[kItems];
 #pragma unroll
@@ -430,53 +438,67 @@ __global__ __launch_bounds__(kThreads, 2) void k_lr_tangent(Dims d, DevTables t,
     }
     __syncthreads();
     // 2. B_a = T_a G_0 on the first determinant's rows and the virtual rows;
-    //    an item is four consecutive slots k of one row (four independent
-    //    sums sharing the row's reads)
-    {
-      const int nq0 = o.R0 * ((nu + 3) / 4), nq1 = o.R1 * ((nd + 3) / 4), nq = nq0 + nq1;
+    //    an item is SL consecutive slots k of one row (independent sums
+    //    sharing the row's reads; SL = 4 from 8 electrons of a spin on)
+    auto step2 = [&](auto sl_tag) {
+      constexpr int SL = decltype(sl_tag)::value;
+      const int nq0 = o.R0 * ((nu + SL - 1) / SL), nq1 = o.R1 * ((nd + SL - 1) / SL), nq = nq0 + nq1;
       for (int q = tid; q < Tc * nq; q += nth) {
         const int col = q / nq, rem = q % nq;
-        const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nk4 = (n + 3) / 4;
-        const int r = rq / nk4, k0 = (rq % nk4) * 4;
+        const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nks = (n + SL - 1) / SL;
+        const int r = rq / nks, k0 = (rq % nks) * SL;
         const double* tb = TB + ((size_t)col * M + ROWORB[s * o.R0 + r]) * N + e0s(s);
         const double* Gs = G0s + (s ? nu * nu : 0);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double acc[SL];
+#pragma unroll
+        for (int u = 0; u < SL; ++u) acc[u] = 0.0;
         for (int i = 0; i < n; ++i) {
           const double x = tb[i];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[u] += x * Gs[i * n + min(k0 + u, n - 1)];
+          for (int u = 0; u < SL; ++u) acc[u] += x * Gs[i * n + min(k0 + u, n - 1)];
         }
         double* B = BM + (size_t)col * bsz + soffB(s) + r * n;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < SL; ++u)
           if (k0 + u < n) B[k0 + u] = acc[u];
       }
-    }
+    };
+    if constexpr (WIDE)
+      step2(std::integral_constant<int, 4>());
+    else
+      step2(std::integral_constant<int, 1>());
     __syncthreads();
     // 3. Xi_a = B_a - Theta N_a on the virtual rows (in place; an item is
-    //    four consecutive slots of one row), and tr N_a, tr N_a^2 per
+    //    SL consecutive slots of one row, as in step 2), and tr N_a, tr N_a^2 per
     //    (coordinate, spin) by one wavefront (lane k: row k), summed across
     //    the lanes in a fixed order
     {
-      const int nq0 = d.nv[0] * ((nu + 3) / 4), nq1 = d.nv[1] * ((nd + 3) / 4), nq = nq0 + nq1;
-      for (int q = tid; q < Tc * nq; q += nth) {
-        const int col = q / nq, rem = q % nq;
-        const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nk4 = (n + 3) / 4;
-        const int v = rq / nk4, k0 = (rq % nk4) * 4;
-        double* B = BM + (size_t)col * bsz + soffB(s);
-        const double* th = THs + soffT(s) + v * n;
-        double acc[4];
+      auto xi = [&](auto sl_tag) {
+        constexpr int SL = decltype(sl_tag)::value;
+        const int nq0 = d.nv[0] * ((nu + SL - 1) / SL), nq1 = d.nv[1] * ((nd + SL - 1) / SL), nq = nq0 + nq1;
+        for (int q = tid; q < Tc * nq; q += nth) {
+          const int col = q / nq, rem = q % nq;
+          const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nks = (n + SL - 1) / SL;
+          const int v = rq / nks, k0 = (rq % nks) * SL;
+          double* B = BM + (size_t)col * bsz + soffB(s);
+          const double* th = THs + soffT(s) + v * n;
+          double acc[SL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = B[(n + v) * n + min(k0 + u, n - 1)];
-        for (int l = 0; l < n; ++l) {
-          const double x = th[l];
+          for (int u = 0; u < SL; ++u) acc[u] = B[(n + v) * n + min(k0 + u, n - 1)];
+          for (int l = 0; l < n; ++l) {
+            const double x = th[l];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[u] -= x * B[l * n + min(k0 + u, n - 1)];
+            for (int u = 0; u < SL; ++u) acc[u] -= x * B[l * n + min(k0 + u, n - 1)];
+          }
+#pragma unroll
+          for (int u = 0; u < SL; ++u)
+            if (k0 + u < n) B[(n + v) * n + k0 + u] = acc[u];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k0 + u < n) B[(n + v) * n + k0 + u] = acc[u];
-      }
+      };
+      if constexpr (WIDE)
+        xi(std::integral_constant<int, 4>());
+      else
+        xi(std::integral_constant<int, 1>());
       const int lane = tid & 63, wv = tid >> 6, nwv = nth >> 6;
       for (int cs = wv; cs < Tc * 2; cs += nwv) {
         const int col = cs / 2, s = cs % 2, n = ns(s);
@@ -690,16 +712,22 @@ void launch_lowrank_tangent(const pn_ctx* c, hipStream_t s, int64_t nw, char* ws
   const Dims& d = c->d;
   const int* flag = reinterpret_cast<const int*>(ws + L.lrflag);
   const int* list = reinterpret_cast<const int*>(ws + L.lrlist);
-  if (L.lds_lr > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lr_tangent),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_lr);
-  hipLaunchKernelGGL(k_lr_tangent, dim3((unsigned)nw), dim3(kThreads), L.lds_lr, s, d, c->t, nw, L.T, L.n_chunks,
-                     reinterpret_cast<const double*>(ws + L.geo), reinterpret_cast<const double*>(ws + L.phi),
-                     reinterpret_cast<const double*>(ws + L.fval), reinterpret_cast<const double*>(ws + L.ftan),
-                     reinterpret_cast<const double*>(ws + L.jtan), reinterpret_cast<const double*>(ws + L.g0),
-                     reinterpret_cast<const double*>(ws + L.theta), reinterpret_cast<const double*>(ws + L.dinv),
-                     reinterpret_cast<const double*>(ws + L.wdet), flag, grad,
-                     reinterpret_cast<double*>(ws + L.partial));
+  auto go = [&](auto kern) {
+    if (L.lds_lr > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)L.lds_lr);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nw), dim3(kThreads), L.lds_lr, s, d, c->t, nw, L.T, L.n_chunks,
+                       reinterpret_cast<const double*>(ws + L.geo), reinterpret_cast<const double*>(ws + L.phi),
+                       reinterpret_cast<const double*>(ws + L.fval), reinterpret_cast<const double*>(ws + L.ftan),
+                       reinterpret_cast<const double*>(ws + L.jtan), reinterpret_cast<const double*>(ws + L.g0),
+                       reinterpret_cast<const double*>(ws + L.theta), reinterpret_cast<const double*>(ws + L.dinv),
+                       reinterpret_cast<const double*>(ws + L.wdet), flag, grad,
+                       reinterpret_cast<double*>(ws + L.partial));
+  };
+  if (std::max(d.n_up, d.n_dn) >= 8 && L.lds_lr > 40 * 1024)
+    go(&k_lr_tangent<true>);
+  else
+    go(&k_lr_tangent<false>);
   // the handed-back walkers: direct determinant tangents
   launch_slater_tangent(c, s, nw, nullptr, ws, L, grad, nullptr, list, list + nw);
 }

@@ -16,7 +16,7 @@ size_t tangent_lds_bytes(const Dims& d, int T, int stage) {
   const int C = T + 1, R = d.N * C;
   const int LDX = ld_pad<TN>(d.DX), LDZ = ld_pad<TN>(d.DZ), LDHZ = std::max(2 * LDZ, LDX);
   const int NCE = chunk_elecs_max(d.N, T);  // electrons a chunk of T coordinates can touch
-  size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + std::max(2 * (size_t)C * LDX, (size_t)NCE * C * LDZ) + (size_t)NCE * (8 * d.N + 4 * d.NN);
+  size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + std::max(2 * (size_t)C * LDX, (size_t)NCE * C * LDZ) + (size_t)NCE * ((stage == 0 && T <= 3 ? 8 : 4) * d.N + 4 * d.NN);
   // stage 2: all electron pairs' w and the chunk rows' w'/d, w'' in LDS
   if (stage >= 2) tn += (size_t)d.n_ee * d.DZ + 2 * (size_t)NCE * (d.N + d.NN) * d.DZ;
   return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN);

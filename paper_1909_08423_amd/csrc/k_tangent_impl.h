@@ -108,6 +108,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   constexpr int JB = JB0 < 1 ? 1 : (JB0 > JBM ? JBM : JB0);
   constexpr int KK = T / 3 + 2;
   constexpr int KO = sizeof(TN) == 4 ? 8 : 4;
+  // row blocks (and the pair-coefficient table) pay off without staged
+  // tables and with narrow chunks (measured: 30-electron chunks of three
+  // coordinates gain, chunks of ten coordinates of ten electrons lose)
+  constexpr bool kRowBlocks = !STAGE && C <= 4;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -138,8 +142,9 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   const int nce_max = chunk_elecs_max(N, T);                    // chunk electrons, at most
   TN* ES = HT + R * LDHZ;  // [2][C][LDX] Jastrow head; in the layers [NCE][C][LDZ] nuclear messages
   TN* ZN = ES;
-  TN* cg = ES + max(2 * C * LDX, nce_max * C * LDZ);            // [NCE][N][8]  pair coefficients (below)
-  TN* cgn = cg + NCE * N * 8;                                   // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
+  // [NCE][N][4] geometry, or [NCE][N][8] pair coefficients (row blocks, below)
+  TN* cg = ES + max(2 * C * LDX, nce_max * C * LDZ);
+  TN* cgn = cg + NCE * N * (kRowBlocks ? 8 : 4);                // [NCE][NN][4] r_k - R_I, 1/|r_k - R_I|
   const int NP = N + d.NN;                                      // partners of a chunk electron
   TN* wvs = cgn + NCE * d.NN * 4;                               // [n_ee][DZ]      (STAGE) w, all ee pairs
   TN* wds = wvs + (STAGE ? d.n_ee * DZ : 0);                    // [NCE][NP][DZ]   (STAGE) w'/d
@@ -154,30 +159,42 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   }
   constexpr int V = 16 / sizeof(TN);  // elements per 16-byte unit
   __syncthreads();
-  // Pair coefficients of chunk electron k and electron j != k, with
-  // u = r_k - r_j, rho = u / |u| and m_alpha = 1 for the chunk's columns of k
-  // (a = 3k + alpha present in the chunk), else 0:
-  //   g_alpha = m_alpha u_alpha,  A = sum m_alpha rho_alpha^2,  B = sum m_alpha (1 - rho_alpha^2)
-  // so that d_a w_kj = (w'/d) g_alpha and sum_a d2_a w_kj = w'' A + (w'/d) B;
-  // zero for j = k.
-  for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
-    const int k = e_lo + q / N, j = q % N;
-    const double u[3] = {rs[3 * k] - rs[3 * j], rs[3 * k + 1] - rs[3 * j + 1], rs[3 * k + 2] - rs[3 * j + 2]};
-    const double inv = j == k ? 0.0 : 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    double A = 0, B = 0;
-    for (int al = 0; al < 3; ++al) {
-      const int col = 3 * k + al - a0;
-      const bool m = j != k && col >= 0 && col < Tc;
-      const double rho = u[al] * inv;
-      cg[8 * q + al] = m ? (TN)u[al] : TN(0);
-      if (m) {
-        A += rho * rho;
-        B += 1.0 - rho * rho;
-      }
+  if constexpr (!kRowBlocks) {
+    // [NCE][N][4]: r_i - r_k and 1/|r_i - r_k| for chunk electron k
+    for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
+      const int k = e_lo + q / N, i = q % N;
+      const double ux = rs[3 * i] - rs[3 * k], uy = rs[3 * i + 1] - rs[3 * k + 1], uz = rs[3 * i + 2] - rs[3 * k + 2];
+      cg[4 * q + 0] = (TN)ux;
+      cg[4 * q + 1] = (TN)uy;
+      cg[4 * q + 2] = (TN)uz;
+      cg[4 * q + 3] = i == k ? TN(0) : (TN)(1.0 / sqrt(ux * ux + uy * uy + uz * uz));
     }
-    cg[8 * q + 3] = (TN)A;
-    cg[8 * q + 4] = (TN)B;
-    cg[8 * q + 5] = cg[8 * q + 6] = cg[8 * q + 7] = TN(0);
+  } else {
+    // Pair coefficients of chunk electron k and electron j != k, with
+    // u = r_k - r_j, rho = u / |u| and m_alpha = 1 for the chunk's columns of k
+    // (a = 3k + alpha present in the chunk), else 0:
+    //   g_alpha = m_alpha u_alpha,  A = sum m_alpha rho_alpha^2,  B = sum m_alpha (1 - rho_alpha^2)
+    // so that d_a w_kj = (w'/d) g_alpha and sum_a d2_a w_kj = w'' A + (w'/d) B;
+    // zero for j = k.
+    for (int q = threadIdx.x; q < NCE * N; q += blockDim.x) {
+      const int k = e_lo + q / N, j = q % N;
+      const double u[3] = {rs[3 * k] - rs[3 * j], rs[3 * k + 1] - rs[3 * j + 1], rs[3 * k + 2] - rs[3 * j + 2]};
+      const double inv = j == k ? 0.0 : 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      double A = 0, B = 0;
+      for (int al = 0; al < 3; ++al) {
+        const int col = 3 * k + al - a0;
+        const bool m = j != k && col >= 0 && col < Tc;
+        const double rho = u[al] * inv;
+        cg[8 * q + al] = m ? (TN)u[al] : TN(0);
+        if (m) {
+          A += rho * rho;
+          B += 1.0 - rho * rho;
+        }
+      }
+      cg[8 * q + 3] = (TN)A;
+      cg[8 * q + 4] = (TN)B;
+      cg[8 * q + 5] = cg[8 * q + 6] = cg[8 * q + 7] = TN(0);
+    }
   }
   for (int q = threadIdx.x; q < NCE * d.NN; q += blockDim.x) {
     const int k = e_lo + q / d.NN, I = q % d.NN;
@@ -236,224 +253,431 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
     __builtin_amdgcn_s_waitcnt(0);  // this wave's loads to LDS have landed
     __syncthreads();
     for (int ch = 0; ch < 2; ++ch) {
-      // Items of a channel: (row block, feature z) for the pair sums, then
-      // (channel 0) (chunk electron, z) for the nuclear messages, which only
-      // rows of the chunk's own electrons have (their product joins channel
-      // 0's).  A row block is RB consecutive rows of one spin; its item
-      // reads each partner's h tangents once for all its rows.
-      const int nbu = (NU + RB - 1) / RB, nbd = (N - NU + RB - 1) / RB;
-      const int n_bulk = (nbu + nbd) * DZ;
-      const int n_items = n_bulk + (ch == 0 ? NCE * DZ : 0);
-      for (int q = threadIdx.x; q < n_items; q += blockDim.x) {
-        if (q >= n_bulk) {
-          const int i = e_lo + (q - n_bulk) / DZ, z = q % DZ;
-          TN* zn = ZN + (i - e_lo) * C * LDZ + z;
+      if constexpr (!kRowBlocks) {
+        // One item per (row, feature z), two partners per step.
+        // channel 0 also takes the nuclear messages, which only rows of the
+        // chunk's own electrons have (extra items; their product joins
+        // channel 0's)
+        const int n_items = N * DZ + (ch == 0 ? NCE * DZ : 0);
+        for (int q = threadIdx.x; q < n_items; q += blockDim.x) {
+          if (q >= N * DZ) {
+            const int i = e_lo + (q - N * DZ) / DZ, z = q % DZ;
+            TN* zn = ZN + (size_t)(i - e_lo) * C * LDZ + z;
+            TN acc[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = 0;
+            const int c0 = 3 * i - a0;
+            for (int I = 0; I < d.NN; ++I) {
+              const TN* gn = cgn + ((size_t)(i - e_lo) * d.NN + I) * 4;
+              const TN y = P[pl.Y + I * DZ + z];
+              TN wd, w2;
+              if constexpr (STAGE) {
+                wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
+                w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
+              } else {
+                const int64_t p = d.n_ee + i * d.NN + I;
+                wd = fd[p * DZ + z];
+                w2 = f2[p * DZ + z];
+              }
+#pragma unroll
+              for (int c = 0; c < T; ++c) {
+                const int al = c - c0;
+                if (al < 0 || al > 2 || c >= Tc) continue;
+                const TN ua = gn[al];
+                const TN ur = ua * gn[3];
+                acc[c] += wd * ua * y;
+                acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) zn[c * LDZ] = acc[c];
+            continue;
+          }
+          const int i = q / DZ, z = q % DZ;
+          const bool up_i = i < NU;
+          // electrons of this channel: same spin (ch 0) or opposite spin (ch 1)
+          const bool want_up = (ch == 0) == up_i;
+          const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
           TN acc[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c] = 0;
-          const int c0 = 3 * i - a0;
-          for (int I = 0; I < d.NN; ++I) {
-            const TN* gn = cgn + ((i - e_lo) * d.NN + I) * 4;
-            const TN y = P[pl.Y + I * DZ + z];
+          if (n > 0) {
+            // Two partners per step; j = i contributes w = 0 (no branch).  All
+            // of a step's LDS reads are issued before its first product (the
+            // scheduling barriers keep the compiler from interleaving read,
+            // wait, multiply per column, which would expose one LDS latency
+            // per column).
+            // (wide FP64 chunks take one partner per step: fewer live registers)
+            constexpr bool kTwo = C * sizeof(TN) <= 48;
+            int j = j_lo;
+            for (; kTwo && j + 1 < j_hi; j += 2) {
+              const int pa = max(pidx[i * N + j], 0), pb = max(pidx[i * N + j + 1], 0);
+              const TN* hja = HT + j * C * LDZ + z;
+              const TN* hjb = hja + C * LDZ;
+              TN ha[C], hb[C];
+#pragma unroll
+              for (int c = 0; c < C; ++c) ha[c] = hja[c * LDZ];
+#pragma unroll
+              for (int c = 0; c < C; ++c) hb[c] = hjb[c * LDZ];
+              const TN wa0 = STAGE ? wvs[pa * DZ + z] : fv[(int64_t)pa * DZ + z];
+              const TN wb0 = STAGE ? wvs[pb * DZ + z] : fv[(int64_t)pb * DZ + z];
+              __builtin_amdgcn_sched_barrier(0);
+              const TN wa = j == i ? TN(0) : wa0, wb = j + 1 == i ? TN(0) : wb0;
+#pragma unroll
+              for (int c = 0; c < C; ++c) acc[c] += wa * ha[c];
+#pragma unroll
+              for (int c = 0; c < C; ++c) acc[c] += wb * hb[c];
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            for (; j < j_hi; ++j) {
+              const int pa = max(pidx[i * N + j], 0);
+              const TN* hja = HT + j * C * LDZ + z;
+              TN ha[C];
+#pragma unroll
+              for (int c = 0; c < C; ++c) ha[c] = hja[c * LDZ];
+              const TN wa0 = STAGE ? wvs[pa * DZ + z] : fv[(int64_t)pa * DZ + z];
+              __builtin_amdgcn_sched_barrier(0);
+              const TN wa = j == i ? TN(0) : wa0;
+#pragma unroll
+              for (int c = 0; c < C; ++c) acc[c] += wa * ha[c];
+            }
+          }
+          TN* zi = ZT + (size_t)i * C * LDZ + z;
+          TN lap = acc[LC];
+          // sources from the coordinates of electron i itself
+          if (i >= e_lo && i <= e_hi) {
+            const TN* gi = cg + (size_t)(i - e_lo) * N * 4;  // r_j - r_i
+            const int c0 = 3 * i - a0;
+            // the chunk's columns of electron i: masks instead of branches, and
+            // clamped column indices for the (masked) reads
+            const TN m0 = (c0 >= 0 && c0 < Tc) ? TN(1) : TN(0);
+            const TN m1 = (c0 + 1 >= 0 && c0 + 1 < Tc) ? TN(1) : TN(0);
+            const TN m2 = (c0 + 2 >= 0 && c0 + 2 < Tc) ? TN(1) : TN(0);
+            const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
+            TN sv0 = 0, sv1 = 0, sv2 = 0;
+            // j = i adds nothing: its staged w'/d, w'' and 1/|r_i - r_j| are zero.
+            // A partner's reads are issued together (FP32: two partners per step).
+            struct Own {
+              TN wd, w2, hj, g0, g1, g2, inv, h0, h1, h2;
+            };
+            auto load_own = [&](int j) {
+              Own o;
+              if constexpr (STAGE) {
+                o.wd = wds[((i - e_lo) * NP + j) * DZ + z];
+                o.w2 = w2s[((i - e_lo) * NP + j) * DZ + z];
+              } else {
+                const int64_t p = max(pidx[i * N + j], 0);
+                o.wd = j == i ? TN(0) : fd[p * DZ + z];
+                o.w2 = j == i ? TN(0) : f2[p * DZ + z];
+              }
+              o.hj = hvs[j * DZ + z];
+              o.g0 = gi[4 * j];
+              o.g1 = gi[4 * j + 1];
+              o.g2 = gi[4 * j + 2];
+              o.inv = gi[4 * j + 3];
+              const TN* hjc = HT + j * C * LDZ + z;
+              o.h0 = n > 0 ? hjc[k0 * LDZ] : TN(0);
+              o.h1 = n > 0 ? hjc[k1 * LDZ] : TN(0);
+              o.h2 = n > 0 ? hjc[k2 * LDZ] : TN(0);
+              return o;
+            };
+            auto use_own = [&](const Own& o) {
+              const TN u0 = -o.g0, u1 = -o.g1, u2 = -o.g2;  // (r_i - r_j)_alpha
+              const TN r0 = u0 * o.inv, r1 = u1 * o.inv, r2 = u2 * o.inv;
+              const TN d0 = m0 * o.wd * u0, d1 = m1 * o.wd * u1, d2 = m2 * o.wd * u2;
+              sv0 += d0 * o.hj;
+              sv1 += d1 * o.hj;
+              sv2 += d2 * o.hj;
+              lap += (m0 * (o.w2 * r0 * r0 + o.wd * (TN(1) - r0 * r0)) + m1 * (o.w2 * r1 * r1 + o.wd * (TN(1) - r1 * r1)) +
+                      m2 * (o.w2 * r2 * r2 + o.wd * (TN(1) - r2 * r2))) * o.hj;
+              lap += TN(2) * (d0 * o.h0 + d1 * o.h1 + d2 * o.h2);  // h tangents are zero at n = 0
+            };
+            int j = j_lo;
+            for (; sizeof(TN) == 4 && j + 1 < j_hi; j += 2) {
+              const Own oa = load_own(j), ob = load_own(j + 1);
+              __builtin_amdgcn_sched_barrier(0);
+              use_own(oa);
+              use_own(ob);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            for (; j < j_hi; ++j) {
+              const Own oa = load_own(j);
+              __builtin_amdgcn_sched_barrier(0);
+              use_own(oa);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+              const int al = c - c0;
+              if (al == 0) acc[c] += sv0;
+              if (al == 1) acc[c] += sv1;
+              if (al == 2) acc[c] += sv2;
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < LC; ++c) zi[c * LDZ] = acc[c];
+          // sources from the coordinates of the chunk's other electrons k (read,
+          // update, write the item's own Z entries; masked columns are left alone)
+          for (int k = max(e_lo, j_lo); k <= min(e_hi, j_hi - 1); ++k) {
+            if (k == i) continue;
+            const TN* gk = cg + ((size_t)(k - e_lo) * N + i) * 4;  // r_i - r_k
             TN wd, w2;
             if constexpr (STAGE) {
-              wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
-              w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
+              wd = wds[((k - e_lo) * NP + i) * DZ + z];
+              w2 = w2s[((k - e_lo) * NP + i) * DZ + z];
             } else {
-              const int p = d.n_ee + i * d.NN + I;
+              const int64_t p = pidx[i * N + k];
               wd = fd[p * DZ + z];
               w2 = f2[p * DZ + z];
             }
+            const TN hk = hvs[k * DZ + z];
+            const TN* hkc = HT + (size_t)k * C * LDZ + z;
+            const int cb = 3 * k - a0;
+            int cc[3];
+            TN ua[3], hc[3], zv[3];
+            bool ok[3];
 #pragma unroll
-            for (int c = 0; c < T; ++c) {
-              const int al = c - c0;
-              if (al < 0 || al > 2 || c >= Tc) continue;
-              const TN ua = gn[al];
-              const TN ur = ua * gn[3];
-              acc[c] += wd * ua * y;
-              acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
+            for (int al = 0; al < 3; ++al) {
+              ok[al] = cb + al >= 0 && cb + al < Tc;
+              cc[al] = min(max(cb + al, 0), LC);
+              ua[al] = gk[al];
+              hc[al] = n > 0 ? hkc[cc[al] * LDZ] : TN(0);
+              zv[al] = zi[cc[al] * LDZ];
             }
-          }
+            const TN inv = gk[3];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int c = 0; c < C; ++c) zn[c * LDZ] = acc[c];
-          continue;
-        }
-        // ---- pair sums of row block blk at feature z ----
-        const int blk = q / DZ, z = q % DZ;
-        const bool upb = blk < nbu;
-        const int i0 = upb ? blk * RB : NU + (blk - nbu) * RB;
-        const int nr = min(RB, (upb ? NU : N) - i0);
-        // electrons of this channel: same spin (ch 0) or opposite spin (ch 1)
-        const bool want_up = (ch == 0) == upb;
-        const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
-        // chunk electrons among the partners (their coordinates move w_ik)
-        const int kk_lo = max(e_lo, j_lo), kk_hi = min(e_hi, j_hi - 1), nk = kk_hi - kk_lo + 1;
-        TN acc[RB][C];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-          for (int c = 0; c < C; ++c) acc[r][c] = 0;
-        // w'/d and w'' of the pairs (row, chunk electron k): requested first,
-        // so their latency overlaps the sums (rows past nr and pairs with
-        // k = i read clamped, valid entries that are never used)
-        TN kwd[RB][KK], kw2[RB][KK];
-        if (nk > 0) {
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            const int ir = i0 + min(r, nr - 1);
-#pragma unroll
-            for (int u = 0; u < KK; ++u) {
-              const int k = kk_lo + min(u, nk - 1);
-              if constexpr (STAGE) {
-                kwd[r][u] = wds[((k - e_lo) * NP + ir) * DZ + z];
-                kw2[r][u] = w2s[((k - e_lo) * NP + ir) * DZ + z];
-              } else {
-                const int o = max(pidx[ir * N + k], 0) * DZ + z;
-                kwd[r][u] = fd[o];
-                kw2[r][u] = f2[o];
-              }
+            for (int al = 0; al < 3; ++al) {
+              const TN ur = ua[al] * inv;
+              const TN dw = -wd * ua[al];  // d/dr_k of w(|r_i - r_k|)
+              const TN m = ok[al] ? TN(1) : TN(0);
+              lap += m * ((w2 * ur * ur + wd * (TN(1) - ur * ur)) * hk + TN(2) * dw * hc[al]);
+              if (ok[al]) zi[cc[al] * LDZ] = zv[al] + dw * hk;
             }
-          }
-        }
-        // sum_j w_ij h_{j,c}: JB partners per step, their w for all RB rows
-        // and their h tangents requested together, and the next step's
-        // requested before this step's products; each h read serves RB rows
-        if (n > 0) {
-          auto fetch = [&](int j, TN (&wv)[JB][RB], TN (&hh)[JB][C]) {
-#pragma unroll
-            for (int jj = 0; jj < JB; ++jj) {
-              const int jc = min(j + jj, j_hi - 1);
-              const TN* hj = HT + jc * C * LDZ + z;
-#pragma unroll
-              for (int c = 0; c < C; ++c) hh[jj][c] = hj[c * LDZ];
-#pragma unroll
-              for (int r = 0; r < RB; ++r) {
-                const int o = max(pidx[(i0 + min(r, nr - 1)) * N + jc], 0) * DZ + z;
-                wv[jj][r] = STAGE ? wvs[o] : fv[o];
-              }
-            }
-          };
-          auto sum = [&](int j, const TN (&wv)[JB][RB], const TN (&hh)[JB][C]) {
-#pragma unroll
-            for (int jj = 0; jj < JB; ++jj) {
-              if (j + jj >= j_hi) break;  // wave-uniform
-#pragma unroll
-              for (int r = 0; r < RB; ++r) {
-                const TN wr = j + jj == i0 + r ? TN(0) : wv[jj][r];  // w_ii = 0
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[r][c] += wr * hh[jj][c];
-              }
-            }
-          };
-          TN wa[JB][RB], ha[JB][C], wb[JB][RB], hb[JB][C];
-          if (j_lo < j_hi) fetch(j_lo, wa, ha);
-          for (int j = j_lo; j < j_hi; j += 2 * JB) {
-            if (j + JB < j_hi) fetch(j + JB, wb, hb);
-            sum(j, wa, ha);
-            if (j + JB >= j_hi) break;
-            if (j + 2 * JB < j_hi) fetch(j + 2 * JB, wa, ha);
-            sum(j + JB, wb, hb);
-          }
-        }
-        // sources from the coordinates of chunk electron k != i: d_a w_ik for
-        // the columns a of k, and their part of the Laplacian column (pair
-        // coefficients g, A, B of (k, i) from the chunk's table)
-        if (nk > 0) {
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            const int i = i0 + min(r, nr - 1);
-#pragma unroll
-            for (int u = 0; u < KK; ++u) {
-              const int k = kk_lo + u;
-              if (u >= nk) break;  // wave-uniform
-              if (k == i) continue;
-              const TN* gk = cg + ((k - e_lo) * N + i) * 8;
-              const TN g0 = gk[0], g1 = gk[1], g2 = gk[2], A = gk[3], B = gk[4];
-              const TN hk = hvs[k * DZ + z];
-              const TN* hkc = HT + k * C * LDZ + z;
-              const int cb = 3 * k - a0;
-              const TN wd = kwd[r][u], w2 = kw2[r][u];
-              TN hsum = 0;
-              if (n > 0)
-                hsum = g0 * hkc[min(max(cb, 0), LC) * LDZ] + g1 * hkc[min(max(cb + 1, 0), LC) * LDZ] +
-                       g2 * hkc[min(max(cb + 2, 0), LC) * LDZ];
-              acc[r][LC] += (w2 * A + wd * B) * hk + TN(2) * wd * hsum;
-              const TN t = wd * hk;
-#pragma unroll
-              for (int c = 0; c < LC; ++c) {
-                const int al = c - cb;
-                if (al >= 0 && al <= 2 && c < Tc) acc[r][c] += (al == 0 ? g0 : (al == 1 ? g1 : g2)) * t;
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          if (r >= nr) break;
-          TN* zi = ZT + (i0 + r) * C * LDZ + z;
-#pragma unroll
-          for (int c = 0; c < C; ++c) zi[c * LDZ] = acc[r][c];
-        }
-        // sources from the coordinates of electron i itself (rows of chunk
-        // electrons only): added to the stored row
-        for (int r = 0; r < nr; ++r) {
-          const int i = i0 + r;
-          if (i < e_lo || i > e_hi) continue;
-          TN* zi = ZT + i * C * LDZ + z;
-          TN lap = zi[LC * LDZ];
-          const TN* gi = cg + (i - e_lo) * N * 8;  // coefficients of the pairs (i, j)
-          const int c0 = 3 * i - a0;
-          // clamped column indices for the reads (masked columns have g = 0)
-          const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
-          TN sv0 = 0, sv1 = 0, sv2 = 0;
-          // partner j != i: d_a w_ij = (w'/d) g_a, and its Laplacian terms
-          auto own = [&](int j, TN wd, TN w2) {
-            const TN* gj = gi + 8 * j;
-            const TN g0 = gj[0], g1 = gj[1], g2 = gj[2], A = gj[3], B = gj[4];
-            const TN hj = hvs[j * DZ + z];
-            TN hsum = 0;
-            if (n > 0) {
-              const TN* hjc = HT + j * C * LDZ + z;
-              hsum = g0 * hjc[k0 * LDZ] + g1 * hjc[k1 * LDZ] + g2 * hjc[k2 * LDZ];
-            }
-            const TN t = wd * hj;
-            sv0 += g0 * t;
-            sv1 += g1 * t;
-            sv2 += g2 * t;
-            lap += (w2 * A + wd * B) * hj + TN(2) * wd * hsum;
-          };
-          const int np = j_hi - j_lo;
-          if constexpr (STAGE) {
-            for (int j = j_lo; j < j_hi; ++j)
-              if (j != i) own(j, wds[((i - e_lo) * NP + j) * DZ + z], w2s[((i - e_lo) * NP + j) * DZ + z]);
-          } else {
-            // w'/d and w'' of the first KO partners requested together
-            TN owd[KO], ow2[KO];
-#pragma unroll
-            for (int u = 0; u < KO; ++u) {
-              const int o = max(pidx[i * N + j_lo + min(u, np - 1)], 0) * DZ + z;
-              owd[u] = fd[o];
-              ow2[u] = f2[o];
-            }
-#pragma unroll
-            for (int u = 0; u < KO; ++u) {
-              if (u >= np) break;  // wave-uniform
-              if (j_lo + u != i) own(j_lo + u, owd[u], ow2[u]);
-            }
-            for (int j = j_lo + KO; j < j_hi; ++j) {
-              if (j == i) continue;
-              const int o = pidx[i * N + j] * DZ + z;
-              own(j, fd[o], f2[o]);
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < LC; ++c) {
-            const int al = c - c0;
-            if (al == 0) zi[c * LDZ] += sv0;
-            if (al == 1) zi[c * LDZ] += sv1;
-            if (al == 2) zi[c * LDZ] += sv2;
           }
           zi[LC * LDZ] = lap;
+        }
+      } else {
+        // Row blocks share each partner's global reads (below).
+        // Items of a channel: (row block, feature z) for the pair sums, then
+        // (channel 0) (chunk electron, z) for the nuclear messages, which only
+        // rows of the chunk's own electrons have (their product joins channel
+        // 0's).  A row block is RB consecutive rows of one spin; its item
+        // reads each partner's h tangents once for all its rows.
+        const int nbu = (NU + RB - 1) / RB, nbd = (N - NU + RB - 1) / RB;
+        const int n_bulk = (nbu + nbd) * DZ;
+        const int n_items = n_bulk + (ch == 0 ? NCE * DZ : 0);
+        for (int q = threadIdx.x; q < n_items; q += blockDim.x) {
+          if (q >= n_bulk) {
+            const int i = e_lo + (q - n_bulk) / DZ, z = q % DZ;
+            TN* zn = ZN + (i - e_lo) * C * LDZ + z;
+            TN acc[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = 0;
+            const int c0 = 3 * i - a0;
+            for (int I = 0; I < d.NN; ++I) {
+              const TN* gn = cgn + ((i - e_lo) * d.NN + I) * 4;
+              const TN y = P[pl.Y + I * DZ + z];
+              TN wd, w2;
+              if constexpr (STAGE) {
+                wd = wds[((i - e_lo) * NP + N + I) * DZ + z];
+                w2 = w2s[((i - e_lo) * NP + N + I) * DZ + z];
+              } else {
+                const int p = d.n_ee + i * d.NN + I;
+                wd = fd[p * DZ + z];
+                w2 = f2[p * DZ + z];
+              }
+#pragma unroll
+              for (int c = 0; c < T; ++c) {
+                const int al = c - c0;
+                if (al < 0 || al > 2 || c >= Tc) continue;
+                const TN ua = gn[al];
+                const TN ur = ua * gn[3];
+                acc[c] += wd * ua * y;
+                acc[LC] += (w2 * ur * ur + wd * (TN(1) - ur * ur)) * y;
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) zn[c * LDZ] = acc[c];
+            continue;
+          }
+          // ---- pair sums of row block blk at feature z ----
+          const int blk = q / DZ, z = q % DZ;
+          const bool upb = blk < nbu;
+          const int i0 = upb ? blk * RB : NU + (blk - nbu) * RB;
+          const int nr = min(RB, (upb ? NU : N) - i0);
+          // electrons of this channel: same spin (ch 0) or opposite spin (ch 1)
+          const bool want_up = (ch == 0) == upb;
+          const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
+          // chunk electrons among the partners (their coordinates move w_ik)
+          const int kk_lo = max(e_lo, j_lo), kk_hi = min(e_hi, j_hi - 1), nk = kk_hi - kk_lo + 1;
+          TN acc[RB][C];
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[r][c] = 0;
+          // w'/d and w'' of the pairs (row, chunk electron k): requested first,
+          // so their latency overlaps the sums (rows past nr and pairs with
+          // k = i read clamped, valid entries that are never used)
+          TN kwd[RB][KK], kw2[RB][KK];
+          if (nk > 0) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+              const int ir = i0 + min(r, nr - 1);
+#pragma unroll
+              for (int u = 0; u < KK; ++u) {
+                const int k = kk_lo + min(u, nk - 1);
+                if constexpr (STAGE) {
+                  kwd[r][u] = wds[((k - e_lo) * NP + ir) * DZ + z];
+                  kw2[r][u] = w2s[((k - e_lo) * NP + ir) * DZ + z];
+                } else {
+                  const int o = max(pidx[ir * N + k], 0) * DZ + z;
+                  kwd[r][u] = fd[o];
+                  kw2[r][u] = f2[o];
+                }
+              }
+            }
+          }
+          // sum_j w_ij h_{j,c}: JB partners per step, their w for all RB rows
+          // and their h tangents requested together, and the next step's
+          // requested before this step's products; each h read serves RB rows
+          if (n > 0) {
+            auto fetch = [&](int j, TN (&wv)[JB][RB], TN (&hh)[JB][C]) {
+#pragma unroll
+              for (int jj = 0; jj < JB; ++jj) {
+                const int jc = min(j + jj, j_hi - 1);
+                const TN* hj = HT + jc * C * LDZ + z;
+#pragma unroll
+                for (int c = 0; c < C; ++c) hh[jj][c] = hj[c * LDZ];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                  const int o = max(pidx[(i0 + min(r, nr - 1)) * N + jc], 0) * DZ + z;
+                  wv[jj][r] = STAGE ? wvs[o] : fv[o];
+                }
+              }
+            };
+            auto sum = [&](int j, const TN (&wv)[JB][RB], const TN (&hh)[JB][C]) {
+#pragma unroll
+              for (int jj = 0; jj < JB; ++jj) {
+                if (j + jj >= j_hi) break;  // wave-uniform
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                  const TN wr = j + jj == i0 + r ? TN(0) : wv[jj][r];  // w_ii = 0
+#pragma unroll
+                  for (int c = 0; c < C; ++c) acc[r][c] += wr * hh[jj][c];
+                }
+              }
+            };
+            TN wa[JB][RB], ha[JB][C], wb[JB][RB], hb[JB][C];
+            if (j_lo < j_hi) fetch(j_lo, wa, ha);
+            for (int j = j_lo; j < j_hi; j += 2 * JB) {
+              if (j + JB < j_hi) fetch(j + JB, wb, hb);
+              sum(j, wa, ha);
+              if (j + JB >= j_hi) break;
+              if (j + 2 * JB < j_hi) fetch(j + 2 * JB, wa, ha);
+              sum(j + JB, wb, hb);
+            }
+          }
+          // sources from the coordinates of chunk electron k != i: d_a w_ik for
+          // the columns a of k, and their part of the Laplacian column (pair
+          // coefficients g, A, B of (k, i) from the chunk's table)
+          if (nk > 0) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+              const int i = i0 + min(r, nr - 1);
+#pragma unroll
+              for (int u = 0; u < KK; ++u) {
+                const int k = kk_lo + u;
+                if (u >= nk) break;  // wave-uniform
+                if (k == i) continue;
+                const TN* gk = cg + ((k - e_lo) * N + i) * 8;
+                const TN g0 = gk[0], g1 = gk[1], g2 = gk[2], A = gk[3], B = gk[4];
+                const TN hk = hvs[k * DZ + z];
+                const TN* hkc = HT + k * C * LDZ + z;
+                const int cb = 3 * k - a0;
+                const TN wd = kwd[r][u], w2 = kw2[r][u];
+                TN hsum = 0;
+                if (n > 0)
+                  hsum = g0 * hkc[min(max(cb, 0), LC) * LDZ] + g1 * hkc[min(max(cb + 1, 0), LC) * LDZ] +
+                         g2 * hkc[min(max(cb + 2, 0), LC) * LDZ];
+                acc[r][LC] += (w2 * A + wd * B) * hk + TN(2) * wd * hsum;
+                const TN t = wd * hk;
+#pragma unroll
+                for (int c = 0; c < LC; ++c) {
+                  const int al = c - cb;
+                  if (al >= 0 && al <= 2 && c < Tc) acc[r][c] += (al == 0 ? g0 : (al == 1 ? g1 : g2)) * t;
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            if (r >= nr) break;
+            TN* zi = ZT + (i0 + r) * C * LDZ + z;
+#pragma unroll
+            for (int c = 0; c < C; ++c) zi[c * LDZ] = acc[r][c];
+          }
+          // sources from the coordinates of electron i itself (rows of chunk
+          // electrons only): added to the stored row
+          for (int r = 0; r < nr; ++r) {
+            const int i = i0 + r;
+            if (i < e_lo || i > e_hi) continue;
+            TN* zi = ZT + i * C * LDZ + z;
+            TN lap = zi[LC * LDZ];
+            const TN* gi = cg + (i - e_lo) * N * 8;  // coefficients of the pairs (i, j)
+            const int c0 = 3 * i - a0;
+            // clamped column indices for the reads (masked columns have g = 0)
+            const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
+            TN sv0 = 0, sv1 = 0, sv2 = 0;
+            // partner j != i: d_a w_ij = (w'/d) g_a, and its Laplacian terms
+            auto own = [&](int j, TN wd, TN w2) {
+              const TN* gj = gi + 8 * j;
+              const TN g0 = gj[0], g1 = gj[1], g2 = gj[2], A = gj[3], B = gj[4];
+              const TN hj = hvs[j * DZ + z];
+              TN hsum = 0;
+              if (n > 0) {
+                const TN* hjc = HT + j * C * LDZ + z;
+                hsum = g0 * hjc[k0 * LDZ] + g1 * hjc[k1 * LDZ] + g2 * hjc[k2 * LDZ];
+              }
+              const TN t = wd * hj;
+              sv0 += g0 * t;
+              sv1 += g1 * t;
+              sv2 += g2 * t;
+              lap += (w2 * A + wd * B) * hj + TN(2) * wd * hsum;
+            };
+            const int np = j_hi - j_lo;
+            if constexpr (STAGE) {
+              for (int j = j_lo; j < j_hi; ++j)
+                if (j != i) own(j, wds[((i - e_lo) * NP + j) * DZ + z], w2s[((i - e_lo) * NP + j) * DZ + z]);
+            } else {
+              // w'/d and w'' of the first KO partners requested together
+              TN owd[KO], ow2[KO];
+#pragma unroll
+              for (int u = 0; u < KO; ++u) {
+                const int o = max(pidx[i * N + j_lo + min(u, np - 1)], 0) * DZ + z;
+                owd[u] = fd[o];
+                ow2[u] = f2[o];
+              }
+#pragma unroll
+              for (int u = 0; u < KO; ++u) {
+                if (u >= np) break;  // wave-uniform
+                if (j_lo + u != i) own(j_lo + u, owd[u], ow2[u]);
+              }
+              for (int j = j_lo + KO; j < j_hi; ++j) {
+                if (j == i) continue;
+                const int o = pidx[i * N + j] * DZ + z;
+                own(j, fd[o], f2[o]);
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < LC; ++c) {
+              const int al = c - c0;
+              if (al == 0) zi[c * LDZ] += sv0;
+              if (al == 1) zi[c * LDZ] += sv1;
+              if (al == 2) zi[c * LDZ] += sv2;
+            }
+            zi[LC * LDZ] = lap;
+          }
         }
       }
       __syncthreads();
