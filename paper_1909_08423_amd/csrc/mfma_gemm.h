@@ -330,9 +330,14 @@ __device__ __forceinline__ void gemm_mfma(const TN* X, int ldx, int rows, int I,
                                                             nullptr, 0, nullptr, epi);
       break;
     default:  // the epilogue acts on the sum of both halves
-      gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
-      gemm_mfma_k<TN, 16, false, false, PAIR, false, EPI>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy,
-                                                            true, bf16, 0, 0, nullptr, 0, nullptr, epi);
+      if constexpr (sizeof(TN) == 4) {  // both halves on each tile: one slab wait, one pass over Y
+        gemm_mfma_k<TN, 16, false, false, PAIR, true, EPI>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16, 0,
+                                                             rows, X + 64, ldx, W + (size_t)64 * O, epi);
+      } else {  // FP64: the halves one after the other (two slabs would spill)
+        gemm_mfma_k<TN, 16, false, false, PAIR>(X, ldx, rows, W, O, O, O, Y, ldy, accumulate, bf16);
+        gemm_mfma_k<TN, 16, false, false, PAIR, false, EPI>(X + 64, ldx, rows, W + (size_t)64 * O, O, O, O, Y, ldy,
+                                                              true, bf16, 0, 0, nullptr, 0, nullptr, epi);
+      }
       break;
   }
 }
