@@ -19,7 +19,9 @@ size_t tangent_lds_bytes(const Dims& d, int T, int stage) {
   size_t tn = (size_t)d.N * d.DZ + (size_t)R * (LDX + LDHZ) + std::max(2 * (size_t)C * LDX, (size_t)NCE * C * LDZ) + (size_t)NCE * ((stage == 0 && T <= 3 ? 8 : 4) * d.N + 4 * d.NN);
   // stage 2: all electron pairs' w and the chunk rows' w'/d, w'' in LDS
   if (stage >= 2) tn += (size_t)d.n_ee * d.DZ + 2 * (size_t)NCE * (d.N + d.NN) * d.DZ;
-  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN);
+  // unstaged chunks of at most 3 coordinates: the row blocks' pair indices
+  const size_t prow = stage == 0 && T <= 3 ? (size_t)((d.n_up + 3) / 4 + (d.n_dn + 3) / 4) * d.N * 4 * sizeof(int) : 0;
+  return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN) + prow;
 }
 
 template size_t tangent_lds_bytes<double>(const Dims&, int, int);

@@ -64,6 +64,23 @@ __device__ __forceinline__ void dma16(uint4* __restrict__ dst, const uint4* __re
 // backflow head, the summed embedding for the Jastrow head):
 //   y_a = s1 v_a (a < 3),   y_L = s1 v_L + s2 sum_a v_a^2
 // with the value pass's slopes s1 = ssp'(u), s2 = ssp''(u) of the feature.
+// h tangents of a 3-coordinate chunk in the FP32 tile layout, where a lane
+// holds the four jet columns of one electron at one feature: stored as one
+// 16-byte unit per (electron, feature), h[j * stride + 4 z + c], so that the
+// message sums read a partner's four columns with one LDS read.
+struct HStore4 {
+  float* h;
+  int n_elec, stride;
+  static constexpr bool kOwnStore = true;
+  template <typename A>
+  __device__ void operator()(int, int, A&) const {}
+  template <typename A>
+  __device__ void store(int rt, int col, const A& c) const {
+    const int j = 4 * rt + (((int)threadIdx.x & 63) >> 4);
+    if (j < n_elec) *reinterpret_cast<float4*>(h + j * stride + 4 * col) = make_float4(c[0], c[1], c[2], c[3]);
+  }
+};
+
 template <typename TN>
 struct HeadAct {
   const TN* s;  // [2][rows][DX] slopes (s1 block, then s2 block)
@@ -112,6 +129,9 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // tables and with narrow chunks (measured: 30-electron chunks of three
   // coordinates gain, chunks of ten coordinates of ten electrons lose)
   constexpr bool kRowBlocks = !STAGE && C <= 4;
+  // chunks of three coordinates in the FP32 tile layout keep the h tangents
+  // interleaved by column ([N][4 DZ + 4]; see HStore4)
+  constexpr bool kH4 = kRowBlocks && C == 4 && sizeof(TN) == 4;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -132,6 +152,9 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   const int e_lo = a0 / 3, e_hi = (a0 + Tc - 1) / 3;
   const int NCE = e_hi - e_lo + 1;
   const int LDX = ld_pad<TN>(DX), LDZ = ld_pad<TN>(DZ), LDHZ = max(2 * LDZ, LDX);
+  // interleaved h tangents: electron stride (16 bytes of padding spread the
+  // four electrons of a tile over the banks) and column step
+  const int SH4 = 4 * DZ + 4, HCS = kH4 ? 1 : LDZ;
   double* rs = reinterpret_cast<double*>(smem);                 // [N][3]
   int* pidx = reinterpret_cast<int*>(rs + 3 * kMaxElec);        // [N][N]
   TN* hvs = reinterpret_cast<TN*>(pidx + ((N * N + 3) & ~3));   // [N][DZ]
@@ -149,6 +172,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   TN* wvs = cgn + NCE * d.NN * 4;                               // [n_ee][DZ]      (STAGE) w, all ee pairs
   TN* wds = wvs + (STAGE ? d.n_ee * DZ : 0);                    // [NCE][NP][DZ]   (STAGE) w'/d
   TN* w2s = wds + (STAGE ? NCE * NP * DZ : 0);                   // [NCE][NP][DZ]   (STAGE) w''
+  int* prow = reinterpret_cast<int*>(wvs);  // (row blocks, never staged) [blocks][N][4] pair indices
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
@@ -194,6 +218,19 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
       cg[8 * q + 3] = (TN)A;
       cg[8 * q + 4] = (TN)B;
       cg[8 * q + 5] = cg[8 * q + 6] = cg[8 * q + 7] = TN(0);
+    }
+    // Pair indices of each row block's RB = 4 rows with every electron j, one
+    // 16-byte unit per (block, j): prow[(blk * N + j) * 4 + r].  Rows past
+    // the block repeat its last row, and (row, row) reads pair 0; the sums
+    // mask both.
+    static_assert(RB == 4, "row blocks of four rows");
+    const int nbu = (NU + RB - 1) / RB, nbd = (N - NU + RB - 1) / RB;
+    for (int q = threadIdx.x; q < (nbu + nbd) * N * RB; q += blockDim.x) {
+      const int r = q % RB, j = (q / RB) % N, blk = q / (RB * N);
+      const bool upb = blk < nbu;
+      const int i0 = upb ? blk * RB : NU + (blk - nbu) * RB;
+      const int nr = min(RB, (upb ? NU : N) - i0);
+      prow[q] = max(pidx[(i0 + min(r, nr - 1)) * N + j], 0);
     }
   }
   for (int q = threadIdx.x; q < NCE * d.NN; q += blockDim.x) {
@@ -248,7 +285,13 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           }
         }
       }
-      if (n > 0) gemm_mfma<TN, true>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
+      if (n > 0) {
+        if constexpr (kH4)
+          gemm_mfma<TN, true, HStore4>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16,
+                                       HStore4{reinterpret_cast<float*>(HT), N, SH4});
+        else
+          gemm_mfma<TN, true>(XT, LDX, R, DX, P + Lp.hW, DZ, HT, LDZ, false, bf16);
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);  // this wave's loads to LDS have landed
     __syncthreads();
@@ -546,14 +589,21 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
 #pragma unroll
               for (int jj = 0; jj < JB; ++jj) {
                 const int jc = min(j + jj, j_hi - 1);
-                const TN* hj = HT + jc * C * LDZ + z;
+                if constexpr (kH4) {
+                  const float4 h4 = *reinterpret_cast<const float4*>(HT + jc * SH4 + 4 * z);
+                  hh[jj][0] = h4.x;
+                  hh[jj][1] = h4.y;
+                  hh[jj][2] = h4.z;
+                  hh[jj][3] = h4.w;
+                } else {
+                  const TN* hj = HT + jc * C * LDZ + z;
 #pragma unroll
-                for (int c = 0; c < C; ++c) hh[jj][c] = hj[c * LDZ];
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                  const int o = max(pidx[(i0 + min(r, nr - 1)) * N + jc], 0) * DZ + z;
-                  wv[jj][r] = STAGE ? wvs[o] : fv[o];
+                  for (int c = 0; c < C; ++c) hh[jj][c] = hj[c * LDZ];
                 }
+                const int4 p4 = *reinterpret_cast<const int4*>(prow + (blk * N + jc) * RB);
+                const int po[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+                for (int r = 0; r < RB; ++r) wv[jj][r] = fv[po[r] * DZ + z];
               }
             };
             auto sum = [&](int j, const TN (&wv)[JB][RB], const TN (&hh)[JB][C]) {
@@ -593,13 +643,13 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
                 const TN* gk = cg + ((k - e_lo) * N + i) * 8;
                 const TN g0 = gk[0], g1 = gk[1], g2 = gk[2], A = gk[3], B = gk[4];
                 const TN hk = hvs[k * DZ + z];
-                const TN* hkc = HT + k * C * LDZ + z;
+                const TN* hkc = kH4 ? HT + k * SH4 + 4 * z : HT + k * C * LDZ + z;
                 const int cb = 3 * k - a0;
                 const TN wd = kwd[r][u], w2 = kw2[r][u];
                 TN hsum = 0;
                 if (n > 0)
-                  hsum = g0 * hkc[min(max(cb, 0), LC) * LDZ] + g1 * hkc[min(max(cb + 1, 0), LC) * LDZ] +
-                         g2 * hkc[min(max(cb + 2, 0), LC) * LDZ];
+                  hsum = g0 * hkc[min(max(cb, 0), LC) * HCS] + g1 * hkc[min(max(cb + 1, 0), LC) * HCS] +
+                         g2 * hkc[min(max(cb + 2, 0), LC) * HCS];
                 acc[r][LC] += (w2 * A + wd * B) * hk + TN(2) * wd * hsum;
                 const TN t = wd * hk;
 #pragma unroll
@@ -636,8 +686,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
               const TN hj = hvs[j * DZ + z];
               TN hsum = 0;
               if (n > 0) {
-                const TN* hjc = HT + j * C * LDZ + z;
-                hsum = g0 * hjc[k0 * LDZ] + g1 * hjc[k1 * LDZ] + g2 * hjc[k2 * LDZ];
+                const TN* hjc = kH4 ? HT + j * SH4 + 4 * z : HT + j * C * LDZ + z;
+                hsum = g0 * hjc[k0 * HCS] + g1 * hjc[k1 * HCS] + g2 * hjc[k2 * HCS];
               }
               const TN t = wd * hj;
               sv0 += g0 * t;

@@ -63,6 +63,13 @@ struct NoEpi {
   template <typename A>
   __device__ void operator()(int, int, A&) const {}
 };
+// An epilogue with `static constexpr bool kOwnStore = true` also stores the
+// tile itself (epi.store(row_tile, column, acc)) in a layout of its own; the
+// product then writes nothing to Y and must not accumulate.
+template <typename E, typename = void>
+struct EpiOwnsStore : std::false_type {};
+template <typename E>
+struct EpiOwnsStore<E, std::void_t<decltype(E::kOwnStore)>> : std::integral_constant<bool, E::kOwnStore> {};
 
 // One wavefront: C += A_tile(16 x I) * B_slab(I x 16), operands in registers
 // (afrag[s] = X[row][g*KQ + s], bfrag[s] = W[g*KQ + s][col]).
@@ -148,6 +155,7 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
   }
   constexpr bool kPair = PAIR && !WIN && sizeof(TN) == 4;
   constexpr bool kEpi = !std::is_same<EPI, NoEpi>::value;
+  constexpr bool kOwn = EpiOwnsStore<EPI>::value;
   // A fragment of row tile rt: 16-byte reads, so each group of 8 lanes
   // covers every LDS bank once (rows are padded by 16 bytes); element-wise
   // reads of the same rows hit each bank up to four times.  Rows and
@@ -244,6 +252,11 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
           epi(rt, col, ca);
           epi(rtb, col, cb);
         }
+        if constexpr (kOwn) {
+          epi.store(rt, col, ca);
+          epi.store(rtb, col, cb);
+          continue;
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = MfmaTile<TN>::row_of(lane, v);
@@ -266,6 +279,10 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
         c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
         c = second(rt, c);
         if constexpr (kEpi) epi(rt, col, c);
+        if constexpr (kOwn) {
+          epi.store(rt, col, c);
+          continue;
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
@@ -281,6 +298,10 @@ __device__ __forceinline__ void gemm_mfma_k(const TN* X, int ldx, int rows, cons
       c = MfmaChain<TN, KQ>::run(afrag, bfrag, c, bf16);
       c = second(rt, c);
       if constexpr (kEpi) epi(rt, col, c);
+      if constexpr (kOwn) {
+        if (colok) epi.store(rt, col, c);  // the epilogue tests its rows
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = (rt << 4) + MfmaTile<TN>::row_of(lane, v);
