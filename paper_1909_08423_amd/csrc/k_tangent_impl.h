@@ -121,7 +121,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // own-row partners whose filter slopes are requested together (KO)
   constexpr int RB = C <= 4 ? 4 : (C <= 5 ? 3 : (C <= 8 ? 2 : 1));
   constexpr int JB0 = 256 / (int)(sizeof(TN) * (RB + C));
-  constexpr int JBM = sizeof(TN) == 4 ? 2 : 1;
+  constexpr int JBM = sizeof(TN) == 4 ? 3 : 1;
   constexpr int JB = JB0 < 1 ? 1 : (JB0 > JBM ? JBM : JB0);
   constexpr int KK = T / 3 + 2;
   constexpr int KO = sizeof(TN) == 4 ? 8 : 4;
