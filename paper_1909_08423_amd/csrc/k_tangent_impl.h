@@ -121,9 +121,9 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // own-row partners whose filter slopes are requested together (KO)
   constexpr int RB = C <= 4 ? 4 : (C <= 5 ? 3 : (C <= 8 ? 2 : 1));
   constexpr int JB0 = 256 / (int)(sizeof(TN) * (RB + C));
-  constexpr int JBM = sizeof(TN) == 4 ? 3 : 1;
+  constexpr int JBM = sizeof(TN) == 4 ? 4 : 1;
   constexpr int JB = JB0 < 1 ? 1 : (JB0 > JBM ? JBM : JB0);
-  constexpr int KK = T / 3 + 2;
+  constexpr int KK = T % 3 == 0 ? T / 3 : T / 3 + 2;  // chunks start at multiples of T
   constexpr int KO = sizeof(TN) == 4 ? 8 : 4;
   // row blocks (and the pair-coefficient table) pay off without staged
   // tables and with narrow chunks (measured: 30-electron chunks of three
