@@ -121,7 +121,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // own-row partners whose filter slopes are requested together (KO)
   constexpr int RB = C <= 4 ? 4 : (C <= 5 ? 3 : (C <= 8 ? 2 : 1));
   constexpr int JB0 = 256 / (int)(sizeof(TN) * (RB + C));
-  constexpr int JBM = sizeof(TN) == 4 ? 4 : 1;
+  constexpr int JBM = sizeof(TN) == 4 ? 3 : 1;
   constexpr int JB = JB0 < 1 ? 1 : (JB0 > JBM ? JBM : JB0);
   constexpr int KK = T % 3 == 0 ? T / 3 : T / 3 + 2;  // chunks start at multiples of T
   constexpr int KO = sizeof(TN) == 4 ? 8 : 4;
@@ -132,6 +132,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // chunks of three coordinates in the FP32 tile layout keep the h tangents
   // interleaved by column ([N][4 DZ + 4]; see HStore4)
   constexpr bool kH4 = kRowBlocks && C == 4 && sizeof(TN) == 4;
+  // the same chunks split the chunk electron's own-row terms over every
+  // wave (partner groups, partial sums added in a fixed order) instead of
+  // leaving them to the one wave that holds the row
+  constexpr bool kSplitOwn = kH4;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -173,6 +177,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   TN* wds = wvs + (STAGE ? d.n_ee * DZ : 0);                    // [NCE][NP][DZ]   (STAGE) w'/d
   TN* w2s = wds + (STAGE ? NCE * NP * DZ : 0);                   // [NCE][NP][DZ]   (STAGE) w''
   int* prow = reinterpret_cast<int*>(wvs);  // (row blocks, never staged) [blocks][N][4] pair indices
+  // (kSplitOwn) [blockDim / DZ][4][DZ] partial own-row sums of the partner groups
+  TN* ownp = reinterpret_cast<TN*>(prow + ((NU + 3) / 4 + (N - NU + 3) / 4) * N * 4);
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) pidx[q] = t.pair_index[q];
@@ -670,6 +676,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           // sources from the coordinates of electron i itself (rows of chunk
           // electrons only): added to the stored row
           for (int r = 0; r < nr; ++r) {
+            if constexpr (kSplitOwn) break;  // below, over all waves
             const int i = i0 + r;
             if (i < e_lo || i > e_hi) continue;
             TN* zi = ZT + i * C * LDZ + z;
@@ -727,6 +734,65 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
               if (al == 2) zi[c * LDZ] += sv2;
             }
             zi[LC * LDZ] = lap;
+          }
+        }
+        if constexpr (kSplitOwn) {
+          // The chunk electron i (one per chunk of three coordinates): thread
+          // (group g, feature z) takes the partners j_lo + g, j_lo + g + G, ...
+          // of i's channel and leaves its partial sums of d_a w_ij h_j (the
+          // three columns of i) and of the Laplacian terms in ownp; after the
+          // barrier the first DZ threads add the G partials, in group order,
+          // to the row the item pass stored.
+          const int i = e_lo;
+          const int G = (int)blockDim.x / DZ, g = (int)threadIdx.x / DZ, z = (int)threadIdx.x % DZ;
+          const bool want_up = (ch == 0) == (i < NU);
+          const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
+          const TN* gi = cg;  // coefficients of the pairs (i, j)
+          const int c0 = 3 * i - a0;
+          const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
+          TN sv0 = 0, sv1 = 0, sv2 = 0, lap = 0;
+          for (int j = j_lo + g; j < j_hi; j += G) {
+            if (j == i) continue;
+            const int o = pidx[i * N + j] * DZ + z;
+            const TN wd = fd[o], w2 = f2[o];
+            const TN* gj = gi + 8 * j;
+            const TN g0 = gj[0], g1 = gj[1], g2 = gj[2], A = gj[3], B = gj[4];
+            const TN hj = hvs[j * DZ + z];
+            TN hsum = 0;
+            if (n > 0) {
+              const TN* hjc = HT + j * SH4 + 4 * z;
+              hsum = g0 * hjc[k0] + g1 * hjc[k1] + g2 * hjc[k2];
+            }
+            const TN t = wd * hj;
+            sv0 += g0 * t;
+            sv1 += g1 * t;
+            sv2 += g2 * t;
+            lap += (w2 * A + wd * B) * hj + TN(2) * wd * hsum;
+          }
+          TN* pg = ownp + g * 4 * DZ + z;
+          pg[0] = sv0;
+          pg[DZ] = sv1;
+          pg[2 * DZ] = sv2;
+          pg[3 * DZ] = lap;
+          __syncthreads();
+          if (g == 0) {
+            TN s0 = 0, s1 = 0, s2 = 0, sl = 0;
+            for (int q = 0; q < G; ++q) {
+              const TN* pq = ownp + q * 4 * DZ + z;
+              s0 += pq[0];
+              s1 += pq[DZ];
+              s2 += pq[2 * DZ];
+              sl += pq[3 * DZ];
+            }
+            TN* zi = ZT + i * C * LDZ + z;
+#pragma unroll
+            for (int c = 0; c < LC; ++c) {
+              const int al = c - c0;
+              if (al == 0) zi[c * LDZ] += s0;
+              if (al == 1) zi[c * LDZ] += s1;
+              if (al == 2) zi[c * LDZ] += s2;
+            }
+            zi[LC * LDZ] += sl;
           }
         }
       }
