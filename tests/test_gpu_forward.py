@@ -140,18 +140,21 @@ def test_antisymmetry_on_gpu(pn):
     np.testing.assert_allclose(b["eloc"], a["eloc"], rtol=1e-9, atol=1e-9)
 
 
-# p99 ratios measured on the fixture batches (ln|psi|, E_loc), about 3x
-# as the gate: FP32 cfg2 1.4e-6 / 2.1e-7, cfg3 1.0e-7 / 6.3e-8, cfg5 4.3e-6 /
-# 2.9e-6; BF16 tangent products cfg2 1.4e-6 / 6.6e-6, cfg3 1.0e-7 / 4.2e-6,
-# cfg5 4.3e-6 / 3.5e-4.
-@pytest.mark.parametrize("idx,prec,bound", [(2, "fp32", 5e-6), (3, "fp32", 3e-7), (5, "fp32", 1.5e-5),
-                                            (2, "bf16", 2e-5), (3, "bf16", 1.5e-5), (5, "bf16", 1.1e-3)])
-def test_mixed_precision_error_statement(pn, idx, prec, bound):
+# p99 ratios measured on the fixture batches (ln|psi|, E_loc; gradient,
+# Laplacian), about 3x as the gate: FP32 cfg2 1.4e-6 / 2.1e-7; 3.6e-5 /
+# 3.6e-5, cfg3 1.0e-7 / 6.3e-8; 1.4e-6 / 1.4e-6, cfg5 4.3e-6 / 2.9e-6;
+# 2.9e-4 / 2.1e-4; BF16 tangent products cfg2 1.4e-6 / 6.6e-6; 1.0e-4 /
+# 5.2e-5, cfg3 1.0e-7 / 4.2e-6; 2.2e-5 / 1.0e-5, cfg5 4.3e-6 / 3.5e-4;
+# 3.6e-3 / 1.9e-3.
+@pytest.mark.parametrize("idx,prec,bound,gbound,lbound", [
+    (2, "fp32", 5e-6, 1.1e-4, 1.1e-4), (3, "fp32", 3e-7, 4.5e-6, 4.5e-6), (5, "fp32", 1.5e-5, 9e-4, 6.5e-4),
+    (2, "bf16", 2e-5, 3e-4, 1.6e-4), (3, "bf16", 1.5e-5, 6.5e-5, 3.2e-5), (5, "bf16", 1.1e-3, 1.1e-2, 5.7e-3)])
+def test_mixed_precision_error_statement(pn, idx, prec, bound, gbound, lbound):
     """Mixed modes: the network in FP32 (or, in the tangent products, BF16
     operands with FP32 accumulation), determinants and E_loc in FP64.  The
-    per-output error against the FP64 oracle is printed; the p99 of the
-    ln|psi| and E_loc ratios must stay within about three times what was
-    measured."""
+    per-output error against the FP64 oracle is printed; the p99 of each
+    output's ratio (ln|psi|, E_loc, gradient, Laplacian) must stay within
+    about three times what was measured."""
     fx = load_fixture(idx)
     w = make_config(idx, n_walkers=4)
     announce(f"{prec} error statement workload {idx}")
@@ -161,6 +164,19 @@ def test_mixed_precision_error_statement(pn, idx, prec, bound):
     print(f"[{prec} cfg{idx}] p50/p99/max: {summ}")
     np.testing.assert_array_equal(out["sign"], fx["sign"])
     assert summ["eloc"][1] < bound and summ["logabs"][1] < bound
+    assert summ["grad"][1] < gbound and summ["lap"][1] < lbound
+
+
+def test_fp32_deterministic_bits(pn):
+    """The FP32 tangent pass at the 30-electron system (row blocks of the
+    pair sums, the chunk electron's own-row terms split over the waves and
+    added in a fixed order) gives the same bits on every run."""
+    w = make_config(5, n_walkers=64)
+    announce("fp32 determinism, workload 5")
+    a, _ = _run(pn, w, w.walkers, pn.PN_PREC_NET_FP32)
+    b, _ = _run(pn, w, w.walkers, pn.PN_PREC_NET_FP32)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
 
 
 # ------------------------------------------------------------- backward ----
