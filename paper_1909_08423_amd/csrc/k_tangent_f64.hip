@@ -21,9 +21,10 @@ size_t tangent_lds_bytes(const Dims& d, int T, int stage) {
   if (stage >= 2) tn += (size_t)d.n_ee * d.DZ + 2 * (size_t)NCE * (d.N + d.NN) * d.DZ;
   // unstaged chunks of at most 3 coordinates: the row blocks' pair indices
   const size_t prow = stage == 0 && T <= 3 ? (size_t)((d.n_up + 3) / 4 + (d.n_dn + 3) / 4) * d.N * 4 * sizeof(int) : 0;
-  // FP32 chunks of 3 coordinates: partial own-row sums, 4 per thread of a
-  // block of at most 512 threads
-  const size_t ownp = stage == 0 && T == 3 && sizeof(TN) == 4 ? (size_t)512 * 4 * sizeof(TN) : 0;
+  // unstaged chunks of 1 or 3 coordinates: partial own-row sums, [groups][4][DZ]
+  // (8 groups in FP32, 2 in FP64, at most one per DZ threads of 512)
+  const int groups = std::min(512 / d.DZ, sizeof(TN) == 4 ? 8 : 2);
+  const size_t ownp = stage == 0 && (T == 1 || T == 3) ? (size_t)groups * 4 * d.DZ * sizeof(TN) : 0;
   return 3 * kMaxElec * sizeof(double) + (size_t)((d.N * d.N + 3) & ~3) * sizeof(int) + tn * sizeof(TN) + prow + ownp;
 }
 

@@ -132,10 +132,12 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // chunks of three coordinates in the FP32 tile layout keep the h tangents
   // interleaved by column ([N][4 DZ + 4]; see HStore4)
   constexpr bool kH4 = kRowBlocks && C == 4 && sizeof(TN) == 4;
-  // the same chunks split the chunk electron's own-row terms over every
-  // wave (partner groups, partial sums added in a fixed order) instead of
-  // leaving them to the one wave that holds the row
-  constexpr bool kSplitOwn = kH4;
+  // row blocks over chunks that touch one electron (T = 1 or 3) split the
+  // chunk electron's own-row terms over partner groups of threads (partial
+  // sums added in a fixed order) instead of leaving them to the one wave
+  // that holds the row: up to 8 groups in FP32, 2 in FP64 (LDS)
+  constexpr bool kSplitOwn = kRowBlocks && (T == 1 || T == 3);
+  constexpr int kSplitG = sizeof(TN) == 4 ? 8 : 2;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   TN* wds = wvs + (STAGE ? d.n_ee * DZ : 0);                    // [NCE][NP][DZ]   (STAGE) w'/d
   TN* w2s = wds + (STAGE ? NCE * NP * DZ : 0);                   // [NCE][NP][DZ]   (STAGE) w''
   int* prow = reinterpret_cast<int*>(wvs);  // (row blocks, never staged) [blocks][N][4] pair indices
-  // (kSplitOwn) [blockDim / DZ][4][DZ] partial own-row sums of the partner groups
+  // (kSplitOwn) [groups][4][DZ] partial own-row sums of the partner groups
   TN* ownp = reinterpret_cast<TN*>(prow + ((NU + 3) / 4 + (N - NU + 3) / 4) * N * 4);
   const double* rw = r + w * N * 3;
   for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) rs[q] = rw[q];
@@ -737,21 +739,21 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           }
         }
         if constexpr (kSplitOwn) {
-          // The chunk electron i (one per chunk of three coordinates): thread
+          // The chunk electron i (the one electron of the chunk): thread
           // (group g, feature z) takes the partners j_lo + g, j_lo + g + G, ...
           // of i's channel and leaves its partial sums of d_a w_ij h_j (the
-          // three columns of i) and of the Laplacian terms in ownp; after the
-          // barrier the first DZ threads add the G partials, in group order,
-          // to the row the item pass stored.
+          // columns of i in the chunk) and of the Laplacian terms in ownp;
+          // after the barrier the first DZ threads add the G partials, in
+          // group order, to the row the item pass stored.
           const int i = e_lo;
-          const int G = (int)blockDim.x / DZ, g = (int)threadIdx.x / DZ, z = (int)threadIdx.x % DZ;
+          const int G = min((int)blockDim.x / DZ, kSplitG), g = (int)threadIdx.x / DZ, z = (int)threadIdx.x % DZ;
           const bool want_up = (ch == 0) == (i < NU);
           const int j_lo = want_up ? 0 : NU, j_hi = want_up ? NU : N;
           const TN* gi = cg;  // coefficients of the pairs (i, j)
           const int c0 = 3 * i - a0;
           const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
           TN sv0 = 0, sv1 = 0, sv2 = 0, lap = 0;
-          for (int j = j_lo + g; j < j_hi; j += G) {
+          for (int j = j_lo + g; g < G && j < j_hi; j += G) {
             if (j == i) continue;
             const int o = pidx[i * N + j] * DZ + z;
             const TN wd = fd[o], w2 = f2[o];
@@ -760,8 +762,8 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
             const TN hj = hvs[j * DZ + z];
             TN hsum = 0;
             if (n > 0) {
-              const TN* hjc = HT + j * SH4 + 4 * z;
-              hsum = g0 * hjc[k0] + g1 * hjc[k1] + g2 * hjc[k2];
+              const TN* hjc = kH4 ? HT + j * SH4 + 4 * z : HT + j * C * LDZ + z;
+              hsum = g0 * hjc[k0 * HCS] + g1 * hjc[k1 * HCS] + g2 * hjc[k2 * HCS];
             }
             const TN t = wd * hj;
             sv0 += g0 * t;
@@ -769,11 +771,13 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
             sv2 += g2 * t;
             lap += (w2 * A + wd * B) * hj + TN(2) * wd * hsum;
           }
-          TN* pg = ownp + g * 4 * DZ + z;
-          pg[0] = sv0;
-          pg[DZ] = sv1;
-          pg[2 * DZ] = sv2;
-          pg[3 * DZ] = lap;
+          if (g < G) {
+            TN* pg = ownp + g * 4 * DZ + z;
+            pg[0] = sv0;
+            pg[DZ] = sv1;
+            pg[2 * DZ] = sv2;
+            pg[3 * DZ] = lap;
+          }
           __syncthreads();
           if (g == 0) {
             TN s0 = 0, s1 = 0, s2 = 0, sl = 0;
