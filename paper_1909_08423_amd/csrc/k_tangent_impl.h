@@ -138,6 +138,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // that holds the row: up to 8 groups in FP32, 2 in FP64 (LDS)
   constexpr bool kSplitOwn = kRowBlocks && (T == 1 || T == 3);
   constexpr int kSplitG = sizeof(TN) == 4 ? 8 : 2;
+  // FP32 chunks of three coordinates also move the chunk electron's terms in
+  // the other rows (pairs (i, k), which only the row blocks of k's channel
+  // have) to a pass over all threads after the same barrier
+  constexpr bool kSplitK = kH4;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           // so their latency overlaps the sums (rows past nr and pairs with
           // k = i read clamped, valid entries that are never used)
           TN kwd[RB][KK], kw2[RB][KK];
-          if (nk > 0) {
+          if (!kSplitK && nk > 0) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
               const int ir = i0 + min(r, nr - 1);
@@ -639,7 +643,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           // sources from the coordinates of chunk electron k != i: d_a w_ik for
           // the columns a of k, and their part of the Laplacian column (pair
           // coefficients g, A, B of (k, i) from the chunk's table)
-          if (nk > 0) {
+          if (!kSplitK && nk > 0) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
               const int i = i0 + min(r, nr - 1);
@@ -752,6 +756,24 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
           const TN* gi = cg;  // coefficients of the pairs (i, j)
           const int c0 = 3 * i - a0;
           const int k0 = min(max(c0, 0), LC), k1 = min(max(c0 + 1, 0), LC), k2 = min(max(c0 + 2, 0), LC);
+          // (kSplitK) rows whose partners in this channel include i: thread
+          // group gk takes rows kr_lo + gk, kr_lo + gk + GR, ... (the rotation
+          // leaves group 0, which also adds the partials, one row fewer); the
+          // slopes of its first two rows are requested now, ahead of the
+          // partner pass and the barrier
+          const bool krows_up = (ch == 0) == (i < NU);
+          const int kr_lo = krows_up ? 0 : NU, kr_hi = krows_up ? NU : N;
+          const int GR = (int)blockDim.x / DZ, gk = (g + GR - 1) % GR;
+          TN kwdp[2], kw2p[2];
+          if constexpr (kSplitK) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int ic = min(kr_lo + gk + u * GR, kr_hi - 1);
+              const int o = max(pidx[ic * N + i], 0) * DZ + z;
+              kwdp[u] = fd[o];
+              kw2p[u] = f2[o];
+            }
+          }
           TN sv0 = 0, sv1 = 0, sv2 = 0, lap = 0;
           for (int j = j_lo + g; g < G && j < j_hi; j += G) {
             if (j == i) continue;
@@ -797,6 +819,37 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
               if (al == 2) zi[c * LDZ] += s2;
             }
             zi[LC * LDZ] += sl;
+          }
+          if constexpr (kSplitK) {
+            // terms of the pairs (r, i) in the rows r != i stored by the item
+            // pass: d_a w_ri for the columns of i, and their part of the
+            // Laplacian column (coefficients g, A, B of (i, r))
+            const TN hk = hvs[i * DZ + z];
+            const TN* hkc = HT + i * SH4 + 4 * z;
+            auto kterm = [&](int r, TN wd, TN w2) {
+              const TN* gk8 = cg + r * 8;
+              const TN g0 = gk8[0], g1 = gk8[1], g2 = gk8[2], A = gk8[3], B = gk8[4];
+              TN hsum = 0;
+              if (n > 0) hsum = g0 * hkc[k0] + g1 * hkc[k1] + g2 * hkc[k2];
+              TN* zr = ZT + r * C * LDZ + z;
+              zr[LC * LDZ] += (w2 * A + wd * B) * hk + TN(2) * wd * hsum;
+              const TN t = wd * hk;
+#pragma unroll
+              for (int c = 0; c < LC; ++c) {
+                const int al = c - c0;
+                if (al >= 0 && al <= 2 && c < Tc) zr[c * LDZ] += (al == 0 ? g0 : (al == 1 ? g1 : g2)) * t;
+              }
+            };
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int r = kr_lo + gk + u * GR;
+              if (r < kr_hi && r != i) kterm(r, kwdp[u], kw2p[u]);
+            }
+            for (int r = kr_lo + gk + 2 * GR; r < kr_hi; r += GR) {
+              if (r == i) continue;
+              const int o = pidx[r * N + i] * DZ + z;
+              kterm(r, fd[o], f2[o]);
+            }
           }
         }
       }
