@@ -138,10 +138,10 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
   // that holds the row: up to 8 groups in FP32, 2 in FP64 (LDS)
   constexpr bool kSplitOwn = kRowBlocks && (T == 1 || T == 3);
   constexpr int kSplitG = sizeof(TN) == 4 ? 8 : 2;
-  // FP32 chunks of three coordinates also move the chunk electron's terms in
-  // the other rows (pairs (i, k), which only the row blocks of k's channel
-  // have) to a pass over all threads after the same barrier
-  constexpr bool kSplitK = kH4;
+  // the same chunks also move the chunk electron's terms in the other rows
+  // (pairs (i, k), which only the row blocks of k's channel have) to a pass
+  // over all threads after the same barrier
+  constexpr bool kSplitK = kSplitOwn;
   extern __shared__ __align__(16) char smem[];
   // XCD-aware order: blocks b, b+8, ... run on one XCD; keep a walker's chunks there.
   const int64_t nb = (int64_t)gridDim.x;
@@ -825,12 +825,12 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_net_tangent(Dims d, DevTables 
             // pass: d_a w_ri for the columns of i, and their part of the
             // Laplacian column (coefficients g, A, B of (i, r))
             const TN hk = hvs[i * DZ + z];
-            const TN* hkc = HT + i * SH4 + 4 * z;
+            const TN* hkc = kH4 ? HT + i * SH4 + 4 * z : HT + i * C * LDZ + z;
             auto kterm = [&](int r, TN wd, TN w2) {
               const TN* gk8 = cg + r * 8;
               const TN g0 = gk8[0], g1 = gk8[1], g2 = gk8[2], A = gk8[3], B = gk8[4];
               TN hsum = 0;
-              if (n > 0) hsum = g0 * hkc[k0] + g1 * hkc[k1] + g2 * hkc[k2];
+              if (n > 0) hsum = g0 * hkc[k0 * HCS] + g1 * hkc[k1 * HCS] + g2 * hkc[k2 * HCS];
               TN* zr = ZT + r * C * LDZ + z;
               zr[LC * LDZ] += (w2 * A + wd * B) * hk + TN(2) * wd * hsum;
               const TN t = wd * hk;
