@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kThreads, WIDE ? 2 : 4) void k_lr_tangent(Dims d, D
   const int tid = threadIdx.x, nth = blockDim.x;
   double* G0s = sm + o.G0;
   double* THs = sm + o.TH;
-  double* TB = sm + o.TB;      // [T][M][N] table derivatives of the chunk
+  double* TB = sm + o.TB;      // [T][N][M] table derivatives of the chunk (orbital fastest)
   double* LT = sm + o.LT;      // [M][N] Laplacian of the table, summed over chunks
   double* BM = sm + o.BM;      // [T][bsz] B_a rows (first determinant's, then virtual) per spin
   double* SS = sm + o.SS;      // [thsz] S = sum_a Xi_a N_a
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kThreads, WIDE ? 2 : 4) void k_lr_tangent(Dims d, D
           const int a = a0 + col, k = a / 3, al = a % 3;
           double v = PF[i * M + mu] * ftv[u];
           if (k == i) v += pj[1 + al] * f;
-          TB[((size_t)col * M + mu) * N + i] = v;
+          TB[((size_t)col * N + i) * M + mu] = v;
         } else if (col == T) {
           double v = PF[i * M + mu] * ftv[u];
           for (int c2 = 0; c2 < Tc; ++c2) {
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kThreads, WIDE ? 2 : 4) void k_lr_tangent(Dims d, D
           const int a = a0 + col, k = a / 3, al = a % 3;
           double v = pj[0] * ft[q];
           if (k == i) v += pj[1 + al] * f;
-          TB[((size_t)col * M + mu) * N + i] = v;
+          TB[((size_t)col * N + i) * M + mu] = v;
         } else if (col == T) {
           double v = pj[0] * ft[q];
           for (int c2 = 0; c2 < Tc; ++c2) {
@@ -447,13 +447,13 @@ __global__ __launch_bounds__(kThreads, WIDE ? 2 : 4) void k_lr_tangent(Dims d, D
         const int col = q / nq, rem = q % nq;
         const int s = rem >= nq0, rq = rem - (s ? nq0 : 0), n = ns(s), nks = (n + SL - 1) / SL;
         const int r = rq / nks, k0 = (rq % nks) * SL;
-        const double* tb = TB + ((size_t)col * M + ROWORB[s * o.R0 + r]) * N + e0s(s);
+        const double* tb = TB + ((size_t)col * N + e0s(s)) * M + ROWORB[s * o.R0 + r];
         const double* Gs = G0s + (s ? nu * nu : 0);
         double acc[SL];
 #pragma unroll
         for (int u = 0; u < SL; ++u) acc[u] = 0.0;
         for (int i = 0; i < n; ++i) {
-          const double x = tb[i];
+          const double x = tb[i * M];
 #pragma unroll
           for (int u = 0; u < SL; ++u) acc[u] += x * Gs[i * n + min(k0 + u, n - 1)];
         }
